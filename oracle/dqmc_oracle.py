@@ -1,0 +1,332 @@
+"""FP64 CPU oracle for DQMC sweeps of the Hubbard model: many short, independent chains.
+
+TEST INFRASTRUCTURE ONLY.  This is the plain, slow reference that the HIP path is checked
+against.  Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of bench.py may import
+it; the product library never does, and this module imports nothing from the product package.
+
+What is computed, in the paper's notation (supplement section I.2, "Determinant Quantum Monte
+Carlo"; the NIMC scheme, Alg. 1 step 4, runs one such chain per starting configuration):
+  * beta is cut into L_tau slices of width dtau (Trotter-Suzuki split of Z);
+  * the Hubbard interaction is decoupled by a discrete HS field s_{i,l} = +-1 with
+    cosh(nu) = exp(U dtau / 2);
+  * the slice propagator is B^sigma_l = exp(sigma nu Diag{s_{.,l}}) exp(-dtau T), sigma = +1 (up),
+    -1 (down), and B^sigma(l2, l1) = B_{l2} ... B_{l1+1};
+  * a field configuration has weight W(s) proportional to prod_sigma det[I + B^sigma(L_tau, 0)].
+The sweep itself (equal-time Green's function, wrap, single-flip Metropolis ratio,
+Sherman-Morrison update, stabilised products) is the textbook DQMC that the paper cites for
+this construction; every step below is derived from the weight above, in the function doing it.
+
+Readings where the paper is silent (listed with reasons in the design notes):
+  * B has the HS factor on the left of exp(-dtau T), as in the definition of B^sigma(l2, l1);
+  * Metropolis acceptance: draw u in [0, 1), accept iff u < R, one uniform per attempt;
+  * a sweep visits slices l = 1 .. L_tau in ascending order and sites i = 0 .. N-1 in each;
+  * stabilisation (fresh G from column-pivoted QR products) after slice l whenever
+    l % stab_every == 0 and after l = L_tau; the wrapped G is replaced by the fresh one;
+  * measurements use the fresh G(L_tau) = G(0) left after the last sweep.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field as dc_field
+from typing import List, Optional, Tuple
+
+import numpy as np
+import scipy.linalg as sla
+
+from .philox import accept_uniform
+
+NEAR_TIE = 1e-9          # |u - R| below this marks a decision that rounding could flip
+FLAG_NONFINITE = 1
+FLAG_NEGATIVE_RATIO = 2
+FLAG_DRIFT = 4
+DRIFT_LIMIT = 1e-3
+
+
+# ------------------------------------------------------------------------------------ model
+def hs_nu(U: float, dtau: float) -> float:
+    """HS coupling: cosh(nu) = exp(U dtau / 2) (discrete HS transformation, SM section I.2)."""
+    return math.acosh(math.exp(0.5 * U * dtau))
+
+
+def kinetic_propagators(T: np.ndarray, dtau: float, mu: float = 0.0):
+    """exp(-dtau (T - mu)) and its inverse exp(+dtau (T - mu)) from the eigenvectors of T."""
+    lam, V = np.linalg.eigh(T - mu * np.eye(T.shape[0]))
+    return (V * np.exp(-dtau * lam)) @ V.T, (V * np.exp(dtau * lam)) @ V.T
+
+
+def slice_B(expK: np.ndarray, nu: float, s_l: np.ndarray, sigma: int) -> np.ndarray:
+    """B^sigma_l = exp(sigma nu Diag{s_l}) exp(-dtau T)."""
+    return np.exp(sigma * nu * s_l.astype(np.float64))[:, None] * expK
+
+
+def slice_Binv(expKinv: np.ndarray, nu: float, s_l: np.ndarray, sigma: int) -> np.ndarray:
+    """(B^sigma_l)^{-1} = exp(+dtau T) exp(-sigma nu Diag{s_l})."""
+    return expKinv * np.exp(-sigma * nu * s_l.astype(np.float64))[None, :]
+
+
+# ------------------------------------------------------------------------ stabilised products
+def udt(X: np.ndarray):
+    """X = U Diag(d) T with U orthogonal, d > 0, from column-pivoted Householder QR (LAPACK).
+
+    X P = Q R; d = |diag R|; the signs of diag R move into U; T = Diag(d)^{-1} S R P^T.
+    """
+    Q, R, piv = sla.qr(X, pivoting=True)
+    r = np.diag(R)
+    sgn = np.where(r < 0.0, -1.0, 1.0)
+    d = np.abs(r)
+    U = Q * sgn[None, :]
+    Rn = (sgn[:, None] * R) / d[:, None]
+    T = np.empty_like(Rn)
+    T[:, piv] = Rn
+    return U, d, T
+
+
+def udt_product(factors: List[np.ndarray], chunk: int, n: int):
+    """UDT of factors[-1] @ ... @ factors[0] (n x n), re-factorised after every `chunk` factors.
+
+    Each chunk is multiplied onto U Diag(d) and factorised again; the new T' multiplies the
+    accumulated T from the left.  The scales of the product live only in d.  No factors: I.
+    """
+    U, d, T = np.eye(n), np.ones(n), np.eye(n)
+    for start in range(0, len(factors), chunk):
+        X = U * d[None, :]
+        for F in factors[start:start + chunk]:
+            X = F @ X
+        U, d, Tn = udt(X)
+        T = Tn @ T
+    return U, d, T
+
+
+def green_two_sided(left, right_t):
+    """G = [I + A B]^{-1} with A = UL DL TL and B^T = UR DR TR, and log|det(I + A B)|.
+
+    Split every scale vector at 1: d = d_big * d_small with d_big = max(d, 1), d_small =
+    min(d, 1).  Then, U being orthogonal,
+        I + A B = UL DLb [DLb^{-1} UL^T UR DRb^{-1} + DLs TL TR^T DRs] DRb UR^T,
+    so with M the bracket, G = UR DRb^{-1} M^{-1} DLb^{-1} UL^T and
+    log|det(I + A B)| = sum log DLb + sum log DRb + log|det M|.
+    """
+    UL, dL, TL = left
+    UR, dR, TR = right_t
+    dLb, dLs = np.maximum(dL, 1.0), np.minimum(dL, 1.0)
+    dRb, dRs = np.maximum(dR, 1.0), np.minimum(dR, 1.0)
+    M = (UL.T @ UR) / dLb[:, None] / dRb[None, :] + dLs[:, None] * (TL @ TR.T) * dRs[None, :]
+    rhs = UL.T / dLb[:, None]
+    G = UR @ (np.linalg.solve(M, rhs) / dRb[:, None])
+    _, logabs = np.linalg.slogdet(M)
+    return G, float(np.sum(np.log(dLb)) + np.sum(np.log(dRb)) + logabs)
+
+
+# -------------------------------------------------------------------------------- the model
+@dataclass
+class Model:
+    T: np.ndarray
+    U: float
+    dtau: float
+    n_slices: int
+    stab_every: int
+    mu: float = 0.0
+
+    def __post_init__(self):
+        self.T = np.asarray(self.T, dtype=np.float64)
+        self.N = self.T.shape[0]
+        self.nu = hs_nu(self.U, self.dtau)
+        self.expK, self.expKinv = kinetic_propagators(self.T, self.dtau, self.mu)
+
+    def B(self, s_l, sigma):
+        return slice_B(self.expK, self.nu, s_l, sigma)
+
+    def Binv(self, s_l, sigma):
+        return slice_Binv(self.expKinv, self.nu, s_l, sigma)
+
+    def green(self, fields: np.ndarray, l: int, sigma: int):
+        """Fresh equal-time G^sigma(l) = [I + B(l, 0) B(L_tau, l)]^{-1} and log|det(I + B(L_tau,0))|.
+
+        Both products are rebuilt from scratch: B(l, 0) from slice 1 upwards and B(L_tau, l)^T
+        = B_{l+1}^T ... B_{L_tau}^T from slice L_tau downwards, each in chunks of stab_every.
+        """
+        Lt = self.n_slices
+        left = udt_product([self.B(fields[k - 1], sigma) for k in range(1, l + 1)],
+                           self.stab_every, self.N)
+        right_t = udt_product([self.B(fields[k - 1], sigma).T for k in range(Lt, l, -1)],
+                              self.stab_every, self.N)
+        return green_two_sided(left, right_t)
+
+    def wrap(self, G, s_l, sigma):
+        """G(l) = B_l G(l-1) B_l^{-1}: [I + B(l,0)B(L,l)]^{-1} conjugated by B_l."""
+        return self.B(s_l, sigma) @ G @ self.Binv(s_l, sigma)
+
+    def ratios(self, G_up, G_dn, s_l):
+        """Per-site ratios for flipping s_{i,l} alone, given G(l) of both spins.
+
+        The flip multiplies B^sigma_l from the left by I + Delta^sigma with Delta^sigma =
+        (exp(-2 sigma nu s_{i,l}) - 1) e_i e_i^T.  With G = [I + A]^{-1}, A = B(l,0)B(L,l):
+        det(I + (I+Delta)A) / det(I + A) = det(I + Delta (I - G)) = 1 + Delta_ii (1 - G_ii).
+        """
+        s = s_l.astype(np.float64)
+        d_up = np.exp(-2.0 * self.nu * s) - 1.0
+        d_dn = np.exp(+2.0 * self.nu * s) - 1.0
+        return 1.0 + d_up * (1.0 - np.diag(G_up)), 1.0 + d_dn * (1.0 - np.diag(G_dn))
+
+
+def measure_from_green(T: np.ndarray, G_up: np.ndarray, G_dn: np.ndarray):
+    """Equal-time estimators for one field (Wick's theorem; spins factorise at fixed field).
+
+    <n_{i sigma}> = 1 - G_ii; double occupancy (1/N) sum_i <n_up n_dn> = (1/N) sum_i
+    (1 - G^up_ii)(1 - G^dn_ii); density (1/N) sum_i (2 - G^up_ii - G^dn_ii); kinetic energy per
+    site (1/N) sum_sigma sum_ij T_ij <c^+_i c_j> = (1/N) sum_sigma sum_ij T_ij (delta_ij - G_ji).
+    """
+    N = T.shape[0]
+    gu, gd = np.diag(G_up), np.diag(G_dn)
+    docc = float(np.sum((1.0 - gu) * (1.0 - gd)) / N)
+    dens = float(np.sum(2.0 - gu - gd) / N)
+    kin = 0.0
+    for G in (G_up, G_dn):
+        kin += float(np.sum(T * (np.eye(N) - G.T)))
+    return docc, dens, kin / N
+
+
+# -------------------------------------------------------------------------------- chains
+@dataclass
+class ChainState:
+    fields: np.ndarray                 # int8 [L_tau][N], modified in place by sweeps
+    seed: int
+    sweeps_done: int = 0
+    G: List[np.ndarray] = dc_field(default_factory=list)   # [G_up, G_dn] = G(0)
+    logdet: List[float] = dc_field(default_factory=lambda: [0.0, 0.0])
+    attempted: int = 0
+    accepted: int = 0
+    near_ties: int = 0
+    max_drift: float = 0.0
+    max_logdet_err: float = 0.0
+    flags: int = 0
+
+
+class OracleChains:
+    """A batch of independent chains on one model, with the semantics of init / sweep / measure."""
+
+    def __init__(self, model: Model, fields: np.ndarray, seeds):
+        self.m = model
+        fields = np.asarray(fields)
+        if fields.ndim == 2:
+            fields = fields[None]
+        if fields.shape[1:] != (model.n_slices, model.N):
+            raise ValueError("fields must be [n_chains][n_slices][N]")
+        if not np.all(np.abs(fields) == 1):
+            raise ValueError("fields must be +-1")
+        self.chains = []
+        for c in range(fields.shape[0]):
+            st = ChainState(fields=fields[c].astype(np.int8).copy(), seed=int(seeds[c]))
+            for k, sigma in enumerate((+1, -1)):
+                G, ld = model.green(st.fields, 0, sigma)
+                st.G.append(G)
+                st.logdet[k] = ld
+            self.chains.append(st)
+
+    # -- one sweep of one chain ---------------------------------------------------------
+    def _sweep_chain(self, st: ChainState):
+        m = self.m
+        Lt, N = m.n_slices, m.N
+        G_up, G_dn = st.G
+        logdet_run = list(st.logdet)
+        for l in range(1, Lt + 1):
+            s_l = st.fields[l - 1]
+            G_up = m.wrap(G_up, s_l, +1)
+            G_dn = m.wrap(G_dn, s_l, -1)
+            for i in range(N):
+                s = float(s_l[i])
+                d_up = math.exp(-2.0 * m.nu * s) - 1.0
+                d_dn = math.exp(+2.0 * m.nu * s) - 1.0
+                r_up = 1.0 + d_up * (1.0 - G_up[i, i])
+                r_dn = 1.0 + d_dn * (1.0 - G_dn[i, i])
+                R = r_up * r_dn
+                u = accept_uniform(st.seed, st.sweeps_done, l - 1, i)
+                st.attempted += 1
+                if not math.isfinite(R):
+                    st.flags |= FLAG_NONFINITE
+                    continue
+                if R < 0.0:
+                    st.flags |= FLAG_NEGATIVE_RATIO
+                    continue
+                if abs(u - R) < NEAR_TIE:
+                    st.near_ties += 1
+                if u < R:
+                    # Sherman-Morrison: G' = G (I + Delta (I - G))^{-1}
+                    #                      = G - (Delta / R_sigma) G[:, i] (e_i - G[i, :])
+                    for k, (d, r) in enumerate(((d_up, r_up), (d_dn, r_dn))):
+                        G = G_up if k == 0 else G_dn
+                        col = G[:, i].copy()
+                        row = -G[i, :].copy()
+                        row[i] += 1.0
+                        G -= (d / r) * np.outer(col, row)
+                    logdet_run[0] += math.log(abs(r_up))
+                    logdet_run[1] += math.log(abs(r_dn))
+                    s_l[i] = -s_l[i]
+                    st.accepted += 1
+            if l % m.stab_every == 0 or l == Lt:
+                for k, sigma in enumerate((+1, -1)):
+                    G_old = G_up if k == 0 else G_dn
+                    G_new, ld = m.green(st.fields, l, sigma)
+                    drift = float(np.max(np.abs(G_old - G_new)))
+                    if not math.isfinite(drift):
+                        st.flags |= FLAG_NONFINITE
+                    st.max_drift = max(st.max_drift, drift)
+                    st.max_logdet_err = max(st.max_logdet_err, abs(ld - logdet_run[k]))
+                    logdet_run[k] = ld
+                    if k == 0:
+                        G_up = G_new
+                    else:
+                        G_dn = G_new
+                if st.max_drift > DRIFT_LIMIT:
+                    st.flags |= FLAG_DRIFT
+        st.G = [G_up, G_dn]
+        st.logdet = logdet_run
+        st.sweeps_done += 1
+
+    def sweep(self, n_sweeps: int = 1, chains: Optional[List[int]] = None):
+        for c in (range(len(self.chains)) if chains is None else chains):
+            for _ in range(n_sweeps):
+                self._sweep_chain(self.chains[c])
+
+    def measure(self):
+        """Per-chain observables from G(0) after the last sweep (one dict per chain)."""
+        out = []
+        for st in self.chains:
+            docc, dens, kin = measure_from_green(self.m.T, st.G[0], st.G[1])
+            out.append(dict(double_occ=docc, density=dens, kinetic=kin,
+                            logdet_up=st.logdet[0], logdet_dn=st.logdet[1],
+                            max_drift=st.max_drift, max_logdet_err=st.max_logdet_err,
+                            attempted=st.attempted, accepted=st.accepted,
+                            near_ties=st.near_ties, flags=st.flags))
+        return out
+
+    def fields(self) -> np.ndarray:
+        return np.stack([st.fields for st in self.chains])
+
+    def green(self) -> np.ndarray:
+        """[n_chains][2][N][N] current G(0) of both spins."""
+        return np.stack([np.stack(st.G) for st in self.chains])
+
+    # -- fixed-field probes (no acceptance, no state change) -----------------------------
+    def debug_green(self, l: int, n_wraps: int) -> np.ndarray:
+        """Fresh G(l) of the current fields, then wrapped through slices l+1 .. l+n_wraps."""
+        out = []
+        for st in self.chains:
+            per = []
+            for sigma in (+1, -1):
+                G, _ = self.m.green(st.fields, l, sigma)
+                for w in range(1, n_wraps + 1):
+                    G = self.m.wrap(G, st.fields[l + w - 1], sigma)
+                per.append(G)
+            out.append(np.stack(per))
+        return np.stack(out)
+
+    def debug_ratios(self, l: int) -> np.ndarray:
+        """[n_chains][2][N]: R^up_i, R^dn_i for flipping s_{i,l} alone, from fresh G(l)."""
+        out = []
+        for st in self.chains:
+            G_up, _ = self.m.green(st.fields, l, +1)
+            G_dn, _ = self.m.green(st.fields, l, -1)
+            r_up, r_dn = self.m.ratios(G_up, G_dn, st.fields[l - 1])
+            out.append(np.stack([r_up, r_dn]))
+        return np.stack(out)

@@ -1,0 +1,326 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: an exact identity of the paper (SM section I.2),
+a closed form, brute-force enumeration, the many-body Fock-space trace, particle-hole symmetry,
+numpy's Philox, or high-precision arithmetic.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dqmc_inputs as di
+from oracle import (Model, OracleChains, hs_nu, philox4x64_10, accept_uniform, udt, udt_product,
+                    measure_from_green)
+import exact_tools as ex
+
+
+# ------------------------------------------------------------------------- random numbers
+@pytest.mark.parametrize("key,ctr", [((123, 456), (5, 6, 7, 8)), ((0, 0), (0, 0, 0, 0)),
+                                     ((2**64 - 1, 7), (2**64 - 1, 3, 0, 1)),
+                                     (((2 << 32) | 17, 0), (63, 39, 49, 1))])
+def test_philox_matches_numpy(key, ctr):
+    # numpy's Philox increments the 256-bit counter before each block.
+    c = sum(int(w) << (64 * k) for k, w in enumerate(ctr))
+    c = (c - 1) % (1 << 256)
+    start = [(c >> (64 * k)) & ((1 << 64) - 1) for k in range(4)]
+    bg = np.random.Philox(counter=np.array(start, dtype=np.uint64),
+                          key=np.array(key, dtype=np.uint64))
+    assert tuple(int(v) for v in bg.random_raw(4)) == philox4x64_10(ctr, key)
+
+
+def test_uniform_mapping():
+    u = accept_uniform(99, 3, 2, 1)
+    w = philox4x64_10((1, 2, 3, 1), (99, 0))[0]
+    assert u == (w >> 11) / 2.0**53 and 0.0 <= u < 1.0
+
+
+def test_seeded_fields_follow_philox_stream():
+    seed, Lt, N = (2 << 32) | 5, 3, 7
+    f = di.seeded_field(seed, Lt, N)
+    for e in range(Lt * N):
+        w = philox4x64_10((e // 4, 0, 0, 0), (seed, 0))[e % 4]
+        assert f.reshape(-1)[e] == (1 if (w & 1) else -1)
+    allf = di.WORKLOADS["square8x8_U4_b4"].fields(4)
+    assert allf.shape == (4, 40, 64) and set(np.unique(allf)) == {-1, 1}
+    assert abs(allf.mean()) < 0.05
+
+
+# ------------------------------------------------------------------------- lattices
+@pytest.mark.parametrize("L", [2, 4, 8])
+def test_square_spectrum(L):
+    k = 2 * np.pi * np.arange(L) / L
+    eps = np.sort((-2.0 * (np.cos(k)[:, None] + np.cos(k)[None, :])).ravel())
+    assert np.allclose(np.linalg.eigvalsh(di.square_hopping(L)), eps, atol=1e-12)
+
+
+@pytest.mark.parametrize("L", [3, 6])
+def test_honeycomb_spectrum(L):
+    k = 2 * np.pi * np.arange(L) / L
+    f = 1 + np.exp(1j * k)[:, None] + np.exp(1j * k)[None, :]
+    eps = np.sort(np.concatenate([np.abs(f).ravel(), -np.abs(f).ravel()]))
+    assert np.allclose(np.linalg.eigvalsh(di.honeycomb_hopping(L)), eps, atol=1e-12)
+
+
+# ------------------------------------------------------------------------- HS and the weight
+def test_hs_identity_on_all_occupations():
+    """exp(-U dtau (n_up - 1/2)(n_dn - 1/2)) = 1/2 e^{-U dtau/4} sum_s e^{nu s (n_up - n_dn)}."""
+    for U, dtau in ((4.0, 0.1), (8.0, 0.1), (3.0, 0.05), (3.83, 0.1)):
+        nu = hs_nu(U, dtau)
+        assert math.isclose(math.cosh(nu), math.exp(U * dtau / 2), rel_tol=1e-15)
+        for nu_, nd in ex.all_occupation_states():
+            lhs = math.exp(-U * dtau * (nu_ - 0.5) * (nd - 0.5))
+            rhs = 0.5 * math.exp(-U * dtau / 4) * sum(math.exp(nu * s * (nu_ - nd)) for s in (1, -1))
+            assert math.isclose(lhs, rhs, rel_tol=1e-14)
+
+
+def test_nu_values():
+    # cosh(nu) = e^{U dtau/2} inverted in closed form: nu = log(x + sqrt(x^2 - 1))
+    for U in (3.0, 3.83, 4.0, 8.0):
+        x = math.exp(U * 0.1 / 2)
+        assert math.isclose(hs_nu(U, 0.1), math.log(x + math.sqrt(x * x - 1)), rel_tol=1e-14)
+
+
+@pytest.mark.parametrize("n_slices,U", [(2, 4.0), (3, 8.0)])
+def test_fock_trace_equals_hs_sum(n_slices, U):
+    """Tr[(e^{-dtau H_U} e^{-dtau H_k})^L] = (e^{-U dtau/4}/2)^{N L} sum_s prod_sigma det(I + B)."""
+    T = di.square_hopping(2)
+    Zf, Df, Ef = ex.fock_trotter(T, U, 0.1, n_slices)
+    Zh, Dh, Eh = ex.enumerate_observables(T, U, 0.1, n_slices)
+    assert math.isclose(Zf, Zh, rel_tol=1e-12)
+    assert math.isclose(Df, Dh, rel_tol=1e-11)
+    assert math.isclose(Ef, Eh, rel_tol=1e-11)
+
+
+def test_oracle_weight_and_green_vs_enumeration():
+    """The oracle's stabilised G(0) and log det on every field of a 2x2, L=3 lattice."""
+    T = di.square_hopping(2)
+    m = Model(T, 4.0, 0.1, 3, 2)
+    fields, w, Gu, Gd = ex.enumerate_fields(T, 4.0, 0.1, 3)
+    for idx in range(0, fields.shape[0], 97):
+        f = fields[idx].astype(np.int8)
+        gu, ldu = m.green(f, 0, +1)
+        gd, ldd = m.green(f, 0, -1)
+        assert np.allclose(gu, Gu[idx], atol=1e-13) and np.allclose(gd, Gd[idx], atol=1e-13)
+        assert math.isclose(ldu + ldd, math.log(w[idx]), rel_tol=1e-12, abs_tol=1e-12)
+
+
+# ------------------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("lattice,L,beta,stab", [("square", 4, 2.0, 10), ("square", 8, 4.0, 10),
+                                                 ("honeycomb", 6, 6.0, 10),
+                                                 ("square", 2, 0.4, 2)])
+def test_free_fermion_green(lattice, L, beta, stab):
+    T = di.hopping(lattice, L)
+    Lt = int(round(beta / 0.1))
+    m = Model(T, 0.0, 0.1, Lt, stab)
+    f = di.seeded_field(11, Lt, T.shape[0])
+    G0 = ex.free_green(T, beta)
+    for l in (0, stab, Lt // 2):
+        G, _ = m.green(f, l, +1)
+        # at U = 0 every slice propagator is exp(-dtau T): G(l) = G(0) for all l
+        assert np.max(np.abs(G - G0)) < 1e-12
+    assert np.allclose(np.diag(G0), 0.5, atol=1e-12)
+    d, n, ek = measure_from_green(T, G0, G0)
+    assert abs(d - 0.25) < 1e-12 and abs(n - 1.0) < 1e-12
+    assert abs(ek - ex.free_kinetic(T, beta)) < 1e-12
+
+
+def test_free_fermion_survey_values():
+    # U = 0 kinetic energies per site, recomputed from the spectrum of T
+    for lattice, L, beta, val in (("square", 4, 2.0, -1.463692229945),
+                                  ("square", 8, 4.0, -1.566637278560),
+                                  ("honeycomb", 6, 6.0, -1.560884583917)):
+        assert abs(ex.free_kinetic(di.hopping(lattice, L), beta) - val) < 1e-11
+
+
+@pytest.mark.parametrize("U,L,beta", [(4.0, 4, 2.0), (4.0, 8, 4.0), (8.0, 4, 4.0)])
+def test_uniform_field_green(U, L, beta):
+    T = di.square_hopping(L)
+    Lt = int(round(beta / 0.1))
+    m = Model(T, U, 0.1, Lt, 10)
+    f = np.ones((Lt, T.shape[0]), dtype=np.int8)
+    for sigma in (+1, -1):
+        G, _ = m.green(f, 0, sigma)
+        Gx = ex.uniform_field_green(T, m.nu, Lt, beta, sigma)
+        assert np.max(np.abs(G - Gx)) < 1e-12
+
+
+# ------------------------------------------------------------------------- particle-hole
+@pytest.mark.parametrize("lattice,L,beta,U", [("square", 4, 2.0, 4.0), ("square", 8, 4.0, 4.0),
+                                              ("honeycomb", 3, 3.0, 3.0)])
+def test_particle_hole_symmetry(lattice, L, beta, U):
+    """mu = 0 on a bipartite lattice: G_dn = D (I - G_up^T) D, det(I+B_dn) = det(I+B_up) e^{-nu sum s}."""
+    T = di.hopping(lattice, L)
+    D = np.diag(di.staggered_sign(lattice, L))
+    Lt = int(round(beta / 0.1))
+    m = Model(T, U, 0.1, Lt, 10)
+    f = di.seeded_field(5, Lt, T.shape[0])
+    for l in (0, 10, Lt - 3):
+        Gu, ldu = m.green(f, l, +1)
+        Gd, ldd = m.green(f, l, -1)
+        assert np.max(np.abs(Gd - D @ (np.eye(T.shape[0]) - Gu.T) @ D)) < 1e-10
+        assert abs(ldd - (ldu - m.nu * float(f.sum()))) < 1e-9 * max(1.0, abs(ldu))
+        # n_up + n_dn = 1 on every site, for every field
+        assert np.allclose(np.diag(Gu) + np.diag(Gd), 1.0, atol=1e-10)
+        if l > 0:
+            ru, rd = m.ratios(Gu, Gd, f[l - 1])
+            assert np.allclose(rd, ru * np.exp(2 * m.nu * f[l - 1]), rtol=1e-10)
+
+
+# ------------------------------------------------------------------------- ratio, update, wrap
+def _direct_green(m, f, l, sigma):
+    """Unstabilised [I + B(l,0) B(L,l)]^{-1} by plain products (small beta only)."""
+    N = m.N
+    A = np.eye(N)
+    for k in range(1, l + 1):
+        A = m.B(f[k - 1], sigma) @ A
+    Bb = np.eye(N)
+    for k in range(l + 1, m.n_slices + 1):
+        Bb = m.B(f[k - 1], sigma) @ Bb
+    M = np.eye(N) + A @ Bb
+    return np.linalg.inv(M), np.linalg.det(M)
+
+
+def test_ratio_equals_determinant_ratio():
+    T = di.square_hopping(4)
+    m = Model(T, 4.0, 0.1, 10, 5)
+    f = di.seeded_field(3, 10, 16)
+    for l in (1, 4, 10):
+        Gu, _ = m.green(f, l, +1)
+        Gd, _ = m.green(f, l, -1)
+        ru, rd = m.ratios(Gu, Gd, f[l - 1])
+        _, du = _direct_green(m, f, l, +1)
+        _, dd = _direct_green(m, f, l, -1)
+        for i in range(16):
+            g = f.copy()
+            g[l - 1, i] = -g[l - 1, i]
+            _, du2 = _direct_green(m, g, l, +1)
+            _, dd2 = _direct_green(m, g, l, -1)
+            assert math.isclose(ru[i], du2 / du, rel_tol=1e-10)
+            assert math.isclose(rd[i], dd2 / dd, rel_tol=1e-10)
+
+
+def test_sherman_morrison_matches_fresh_inverse():
+    """The oracle's update path (wrap + Sherman-Morrison on every accept) against fresh inverses.
+
+    Its drift record compares the wrapped and updated G with G rebuilt from the new fields at
+    every stabilisation point; a wrong sign, index or factor in the update would show there.
+    The rank-1 formula itself is checked against G (I + Delta (I - G))^{-1} by a linear solve.
+    """
+    T = di.square_hopping(4)
+    m = Model(T, 4.0, 0.1, 20, 4)
+    f = di.seeded_field(8, 20, 16)
+    oc = OracleChains(m, f[None], [8])
+    oc.sweep(2)
+    st = oc.chains[0]
+    assert st.max_drift < 1e-10 and st.accepted > 50 and st.max_logdet_err < 1e-10
+    fu, _ = _direct_green(m, st.fields, 0, +1)
+    assert np.max(np.abs(st.G[0] - fu)) < 1e-11
+    # rank-1 update vs the definition through a solve, and vs the flipped field's fresh G
+    l, i = 7, 5
+    G, _ = _direct_green(m, st.fields, l, +1)
+    s = float(st.fields[l - 1, i])
+    d = math.exp(-2.0 * m.nu * s) - 1.0
+    Dl = np.zeros((16, 16))
+    Dl[i, i] = d
+    G_def = G @ np.linalg.inv(np.eye(16) + Dl @ (np.eye(16) - G))
+    g = st.fields.copy()
+    g[l - 1, i] = -g[l - 1, i]
+    G_new, _ = _direct_green(m, g, l, +1)
+    assert np.max(np.abs(G_def - G_new)) < 1e-11
+
+
+def test_wrap_matches_fresh():
+    T = di.square_hopping(8)
+    m = Model(T, 4.0, 0.1, 40, 10)
+    f = di.seeded_field(13, 40, 64)
+    G, _ = m.green(f, 10, +1)
+    for w in range(1, 11):
+        G = m.wrap(G, f[10 + w - 1], +1)
+    G20, _ = m.green(f, 20, +1)
+    assert np.max(np.abs(G - G20)) < 1e-10
+
+
+def test_udt_factorisation():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((24, 24)) * np.logspace(0, 12, 24)[None, :]
+    U, d, T = udt(X)
+    assert np.allclose(U.T @ U, np.eye(24), atol=1e-14)
+    assert np.allclose((U * d) @ T, X, rtol=0, atol=1e-14 * np.abs(X).max())
+    assert np.all(d > 0) and np.all(np.diff(d) <= 1e-9 * d[:-1])   # pivoting sorts the scales
+
+
+def test_green_vs_high_precision():
+    """Stabilised G(0) of a strongly ill-conditioned product against 60-digit arithmetic."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    T = di.square_hopping(2)
+    Lt, U = 100, 8.0
+    m = Model(T, U, 0.1, Lt, 10)
+    f = di.seeded_field(21, Lt, 4)
+    lam, V = np.linalg.eigh(T)
+    Vm = mpmath.matrix(V.tolist())
+    K = Vm * mpmath.diag([mpmath.exp(-0.1 * mpmath.mpf(x)) for x in lam]) * Vm.T
+    nu = mpmath.acosh(mpmath.exp(mpmath.mpf(U) * mpmath.mpf("0.1") / 2))
+    for sigma in (+1, -1):
+        P = mpmath.eye(4)
+        for l in range(Lt):
+            V_l = mpmath.diag([mpmath.exp(sigma * nu * int(s)) for s in f[l]])
+            P = V_l * K * P
+        Gx = (mpmath.eye(4) + P) ** -1
+        G, ld = m.green(f, 0, sigma)
+        err = max(abs(float(Gx[i, j]) - G[i, j]) for i in range(4) for j in range(4))
+        # K enters both sides rounded to FP64; 100 slices of U=8 amplify that to ~1e-12
+        assert err < 1e-11 * max(1.0, float(np.abs(G).max()))
+        assert abs(float(mpmath.log(abs(mpmath.det(mpmath.eye(4) + P)))) - ld) < 1e-9
+
+
+# ------------------------------------------------------------------------- chain behaviour
+def test_resume_is_bitwise():
+    T = di.square_hopping(4)
+    m = Model(T, 4.0, 0.1, 20, 10)
+    f = di.seeded_fields([1, 2], 20, 16)
+    a = OracleChains(m, f, [1, 2])
+    a.sweep(4)
+    b = OracleChains(m, f, [1, 2])
+    b.sweep(2)
+    b.sweep(2)
+    assert np.array_equal(a.fields(), b.fields())
+    assert np.array_equal(a.green(), b.green())
+
+
+def test_logdet_bookkeeping_and_drift():
+    T = di.square_hopping(4)
+    m = Model(T, 4.0, 0.1, 20, 10)
+    oc = OracleChains(m, di.seeded_fields([7], 20, 16), [7])
+    oc.sweep(3)
+    o = oc.measure()[0]
+    # ten wraps and ~100 rank-1 updates between refreshes from a random start: ~1e-9 drift
+    assert o["max_logdet_err"] < 1e-8 and o["max_drift"] < 1e-8 and o["flags"] == 0
+    assert o["attempted"] == 3 * 20 * 16 and 0 < o["accepted"] < o["attempted"]
+    # log det from a plain determinant at this small beta
+    _, du = _direct_green(m, oc.chains[0].fields, 0, +1)
+    assert math.isclose(o["logdet_up"], math.log(du), rel_tol=1e-11)
+    assert abs(o["density"] - 1.0) < 1e-10   # half filling holds field by field
+
+
+@pytest.mark.slow
+def test_chain_statistics_match_enumeration():
+    """2x2, U=4, L_tau=4: oracle chains sample W(s); <D> and <E_k> within 4 sigma of exact."""
+    T = di.square_hopping(2)
+    Lt = 4
+    _, Dx, Ex = ex.enumerate_observables(T, 4.0, 0.1, Lt)
+    m = Model(T, 4.0, 0.1, Lt, 2)
+    n_chains, burn, n_meas = 24, 20, 150
+    seeds = list(range(100, 100 + n_chains))
+    oc = OracleChains(m, di.seeded_fields(seeds, Lt, 4), seeds)
+    oc.sweep(burn)
+    sums = np.zeros((n_chains, 2))
+    for _ in range(n_meas):
+        oc.sweep(1)
+        for c, o in enumerate(oc.measure()):
+            sums[c] += (o["double_occ"], o["kinetic"])
+    means = sums / n_meas
+    for k, exact in enumerate((Dx, Ex)):
+        mu, se = means[:, k].mean(), means[:, k].std(ddof=1) / math.sqrt(n_chains)
+        assert abs(mu - exact) < 4 * se + 1e-12, (k, mu, se, exact)
