@@ -1,0 +1,166 @@
+/*
+ * dqmc.h -- C ABI of the MI355X batched DQMC sweep library (libdqmc.so).
+ *
+ * The library runs step 4 of the NIMC scheme (Alg. 1 of the paper): one short determinant QMC
+ * Markov chain per starting Hubbard-Stratonovich (HS) configuration, many independent chains at
+ * once, for the Hubbard model of eq. (3).  The problem is the one of supplement section I.2:
+ * the inverse temperature beta = n_slices * dtau is cut into L_tau = n_slices Trotter slices,
+ * the interaction is decoupled by a discrete HS field s_{i,l} = +-1 with cosh(nu) = e^{U dtau/2},
+ * the slice propagator is B^sigma_l = e^{sigma nu Diag(s_l)} e^{-dtau T} and a field has weight
+ * prod_sigma det[I + B^sigma(L_tau, 0)].  A sweep attempts one single-site flip at every
+ * (slice, site) of the field (definition of a sweep in supplement section I.3).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns a dqmc_status; nothing throws or aborts across the ABI.
+ *   - Device memory is owned by the caller (e.g. torch tensors); the library never calls
+ *     hipMalloc or hipFree.  It owns only the opaque host-side dqmc_batch handle.
+ *   - "stream" is a hipStream_t (NULL = the default stream).  Calls enqueue work on it and
+ *     return; only dqmc_init_chains and dqmc_measure wait for their own work (to report input
+ *     errors and numerical flags).  A handle is used from one stream at a time and is not
+ *     thread-safe.
+ *   - Matrices are row-major.  Sites are 0 .. N-1, slices l = 1 .. L_tau are stored at
+ *     index l-1 of the field, spins are index 0 (up, sigma = +1) and 1 (down, sigma = -1).
+ *   - dqmc_last_error() returns a thread-local message describing the last failure.
+ */
+#ifndef DQMC_H
+#define DQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DQMC_OK = 0,
+  DQMC_EINVAL = -1,   /* bad shape or parameter, or a field value other than +-1 */
+  DQMC_ENOMEM = -2,   /* the caller's workspace is smaller than dqmc_workspace_bytes */
+  DQMC_EDEVICE = -3,  /* a HIP runtime error (message in dqmc_last_error) */
+  DQMC_ENUMERIC = -4, /* at least one chain raised a numerical flag (see dqmc_obs.flags) */
+  DQMC_EBUSY = -5     /* reserved: the handle is in use */
+} dqmc_status;
+
+typedef enum {
+  DQMC_FP64 = 0,       /* everything in FP64 */
+  DQMC_FP32_WRAP = 1   /* wraps and delayed updates in FP32 (MFMA); QR/UDT stabilisation,
+                          fresh Green's functions and every acceptance ratio stay in FP64 */
+} dqmc_precision;
+
+/* Per-chain flags (dqmc_obs.flags) */
+#define DQMC_FLAG_NONFINITE 1   /* a ratio or a Green's function went non-finite */
+#define DQMC_FLAG_NEGATIVE 2    /* R < 0 (cannot happen at half filling on a bipartite lattice) */
+#define DQMC_FLAG_DRIFT 4       /* |G_wrapped - G_fresh| exceeded the precision's limit */
+#define DQMC_FLAG_SINGULAR 8    /* a zero pivot in QR or LU */
+
+/* The model (supplement section I.2).  All values are read during dqmc_init_chains. */
+typedef struct {
+  int32_t n_sites;          /* N >= 1 */
+  const double* hopping;    /* HOST, N*N row-major symmetric T (T_ij = -t per bond); copied */
+  double U;                 /* on-site repulsion (>= 0) */
+  double mu;                /* chemical potential: T -> T - mu I (0 = half filling) */
+  double dtau;              /* Trotter step; beta = n_slices * dtau */
+  int32_t n_slices;         /* L_tau >= 1 */
+  int32_t stab_every;       /* FP64: slices between QR/UDT stabilisations (fresh G); >= 1 */
+  int32_t refresh_every;    /* FP32_WRAP: slices between FP64 fresh-G refreshes (0 = stab_every).
+                               The refresh points are also the stabilisation points. */
+  int32_t delay_rank;       /* k: sites per delayed-update block (0 = library default) */
+  int32_t precision;        /* dqmc_precision */
+} dqmc_model;
+
+/* Observables of one chain, written by dqmc_measure (device memory, one per chain).  The
+ * estimators use the equal-time Green's function G(0) = G(L_tau) that the last stabilisation
+ * of the last sweep left (a pure function of the current field). */
+typedef struct {
+  double double_occ;      /* (1/N) sum_i <n_i,up n_i,dn> */
+  double density;         /* (1/N) sum_i <n_i,up + n_i,dn> */
+  double kinetic;         /* (1/N) sum_sigma sum_ij T_ij <c+_i c_j> */
+  double logdet_up;       /* log|det(I + B^up(L_tau, 0))| */
+  double logdet_dn;
+  double max_drift;       /* max over stabilisations of max|G_wrapped - G_fresh| */
+  double max_logdet_err;  /* max |log det from accumulated log R - fresh log det| */
+  int64_t attempted;      /* flips attempted (sweeps * L_tau * N) */
+  int64_t accepted;
+  int64_t near_ties;      /* decisions with |u - R| < 1e-9 */
+  int64_t sweeps_done;    /* global sweep counter of the chain (RNG counter, resume point) */
+  int32_t flags;          /* DQMC_FLAG_* */
+  int32_t reserved;
+} dqmc_obs;
+
+typedef struct dqmc_batch dqmc_batch;   /* opaque host handle */
+
+/* Device bytes one chain needs (the admission unit of a memory budget). */
+size_t dqmc_chain_bytes(const dqmc_model* m);
+
+/* Device workspace for n_chains chains of model m (shared constants + per-chain state). */
+size_t dqmc_workspace_bytes(const dqmc_model* m, int32_t n_chains);
+
+/* Create n_chains chains and compute their initial Green's functions G(0).
+ *   fields: DEVICE int8 [n_chains][n_slices][N] of +-1 (copied into the workspace), or NULL to
+ *           draw each chain's field from its seed (Philox4x64-10, key (seed, 0): element
+ *           e = l*N + i is +1 iff the low bit of raw output word e is 1).
+ *   seeds:  HOST uint64 [n_chains]; the key of each chain's acceptance random numbers.
+ *   workspace: DEVICE, at least dqmc_workspace_bytes(m, n_chains) bytes, 256-byte aligned,
+ *           owned by the caller and kept alive until dqmc_destroy.
+ * Waits for its own work; returns EINVAL for a field value other than +-1. */
+dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_chains,
+                             const int8_t* fields, const uint64_t* seeds, void* workspace,
+                             size_t ws_bytes, void* stream);
+
+/* Run n_sweeps Metropolis sweeps on every chain of the batch (one persistent launch). */
+dqmc_status dqmc_sweep(dqmc_batch* b, int32_t n_sweeps, void* stream);
+
+/* Sweep several batches (e.g. different lattice sizes) together: one launch per batch, all
+ * enqueued before any waits, the batches overlapping on the device through forked streams. */
+dqmc_status dqmc_sweep_multi(dqmc_batch* const* bs, const int32_t* n_sweeps, int32_t n,
+                             void* stream);
+
+/* Per-chain observables into obs (DEVICE [n_chains]); if green != NULL also both spins' G(0)
+ * into green (DEVICE double [n_chains][2][N][N]).  Waits; returns ENUMERIC if any flag is set
+ * (the outputs are written regardless). */
+dqmc_status dqmc_measure(dqmc_batch* b, dqmc_obs* obs, double* green, void* stream);
+
+/* Current fields into out (DEVICE int8 [n_chains][n_slices][N]). */
+dqmc_status dqmc_get_fields(dqmc_batch* b, int8_t* out, void* stream);
+
+/* Release the host handle (the workspace stays the caller's). */
+dqmc_status dqmc_destroy(dqmc_batch* b);
+
+const char* dqmc_last_error(void);
+
+/* Numbers the library chose: site-block size k, stabilisation interval, LDS bytes of the sweep
+ * kernel, and the kernel variant (0 = LDS-resident Green's function, 1 = global-memory). */
+dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int32_t* lds_bytes,
+                            int32_t* variant);
+
+/* ---- fixed-field probes for parity tests: no acceptance, no change of fields or G(0) ---- */
+
+/* Fresh G^sigma(slice) = [I + B(slice,0) B(L_tau,slice)]^{-1} of every chain's current field,
+ * then n_wraps wraps G <- B_l G B_l^{-1} (l = slice+1 .. slice+n_wraps) in the batch's wrap
+ * precision.  out: DEVICE double [n_chains][2][N][N].  0 <= slice, slice + n_wraps <= L_tau. */
+dqmc_status dqmc_debug_green(dqmc_batch* b, int32_t slice, int32_t n_wraps, double* out,
+                             void* stream);
+
+/* Ratios R^sigma_i = 1 + Delta^sigma_i (1 - G^sigma_ii(slice)) for flipping s_{i,slice} alone,
+ * from the fresh G(slice).  out: DEVICE double [n_chains][2][N].  1 <= slice <= L_tau. */
+dqmc_status dqmc_debug_ratios(dqmc_batch* b, int32_t slice, double* out, void* stream);
+
+/* The propagators e^{-dtau (T - mu)} and e^{+dtau (T - mu)} the batch computed on the device.
+ * out: DEVICE double [2][N][N]. */
+dqmc_status dqmc_debug_propagators(dqmc_batch* b, double* out, void* stream);
+
+/* Raw Philox4x64-10 blocks of the device generator: for counters (c0 + j, c1, c2, c3),
+ * j = 0 .. n_blocks-1, key (k0, k1), the four words into out (DEVICE uint64 [n_blocks][4]). */
+dqmc_status dqmc_debug_philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
+                              uint64_t c3, int32_t n_blocks, uint64_t* out, void* stream);
+
+/* One 16x16x4 matrix-core product per precision: A (16x4), B (4x16) row-major DEVICE inputs,
+ * C = A B written row-major into out64 (double[256]) and out32 (float[256]); checks the lane
+ * layout the library assumes for each instruction. */
+dqmc_status dqmc_debug_mfma(const double* a64, const double* b64, double* out64,
+                            const float* a32, const float* b32, float* out32, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DQMC_H */

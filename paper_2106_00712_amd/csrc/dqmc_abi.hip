@@ -1,0 +1,610 @@
+// Host side of libdqmc.so: the C ABI declared in include/dqmc.h, the workspace layout, and the
+// kernels that are not part of the per-chain sweep (model constants, measurements, probes).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dqmc.h"
+#include "dqmc_device.hpp"
+
+using namespace dqmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+dqmc_status fail(dqmc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(DQMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------------ model constants
+// e^{A} for A = sign * (-dtau) (T - mu I) by scaling and squaring of the degree-18 Taylor
+// polynomial (Horner form, one MFMA product per degree) on one workgroup:
+//   E_18 = I,  E_{k-1} = I + (A / 2^s) E_k / k,  then E_0 squared s times.
+// ||A / 2^s||_1 <= 1/2, so the truncation error is below 1e-22 relative.
+constexpr int TAYLOR_DEGREE = 18;
+
+__global__ __launch_bounds__(NT) void constants_kernel(int n, int np, double dtau, double mu, int s,
+                                                      const double* Tp, double* A, double* E0,
+                                                      double* E1, double* expK, double* expKinv,
+                                                      float* expK32, float* expKinv32, double* eye,
+                                                      double* ones, int* err) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *err = 0;
+  for (int e = tid; e < np * np; e += NT) {
+    int i = e / np, j = e - i * np;
+    eye[e] = (i == j && i < n) ? 1.0 : 0.0;
+  }
+  for (int i = tid; i < np; i += NT) ones[i] = 1.0;
+  const double scale = std::ldexp(dtau, -s);
+  for (int pass = 0; pass < 2; ++pass) {
+    const double sg = pass == 0 ? -1.0 : 1.0;   // e^{-dtau(T-mu)} then e^{+dtau(T-mu)}
+    for (int e = tid; e < np * np; e += NT) {
+      int i = e / np, j = e - i * np;
+      double v = 0.0;
+      if (i < n && j < n) v = sg * scale * (Tp[e] - (i == j ? mu : 0.0));
+      A[e] = v;
+      E0[e] = (i == j && i < n) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double* cur = E0;
+    double* nxt = E1;
+    for (int k = TAYLOR_DEGREE; k >= 1; --k) {
+      const double ik = 1.0 / k;
+      wg_gemm<double>(1, np, np, np, A, A, np, 1, cur, cur, np, 1, [&](int, int i, int j, double v) {
+        nxt[i * np + j] = ((i == j && i < n) ? 1.0 : 0.0) + v * ik;
+      });
+      __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
+    }
+    for (int q = 0; q < s; ++q) {
+      wg_gemm<double>(1, np, np, np, cur, cur, np, 1, cur, cur, np, 1,
+                      [&](int, int i, int j, double v) { nxt[i * np + j] = v; });
+      __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
+    }
+    double* dst = pass == 0 ? expK : expKinv;
+    float* dst32 = pass == 0 ? expK32 : expKinv32;
+    for (int e = tid; e < np * np; e += NT) {
+      dst[e] = cur[e];
+      dst32[e] = (float)cur[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------ sweep kernel
+template <typename WT, bool SMALL>
+__global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
+  extern __shared__ double lds[];
+  const int chain = blockIdx.x;
+  if (chain >= a.n_chains) return;
+  Ctx<WT> c = make_ctx<WT, SMALL>(a, chain, lds);
+  if (a.op == OP_INIT) {
+    if (threadIdx.x == 0) {
+      ChainStats* st = c.st;
+      st->seed = a.seeds[chain];
+      st->sweeps_done = st->attempted = st->accepted = st->near_ties = 0;
+      st->max_drift = st->max_logdet_err = 0.0;
+      st->logdet[0] = st->logdet[1] = 0.0;
+      st->flags = 0;
+      st->pad = 0;
+    }
+    __syncthreads();
+    op_init(c, chain);
+  } else if (a.op == OP_SWEEP) {
+    op_sweep(c, a.n_sweeps);
+  } else if (a.op == OP_DEBUG_GREEN) {
+    op_debug_green(c, chain);
+  } else if (a.op == OP_DEBUG_RATIOS) {
+    op_debug_ratios(c, chain);
+  }
+}
+
+// ------------------------------------------------------------------------ measurements
+// Equal-time estimators of one chain from its fresh G(0) (Wick's theorem at a fixed field):
+// <n_i sigma> = 1 - G_ii, double occupancy (1/N) sum_i (1 - G^up_ii)(1 - G^dn_ii), density,
+// kinetic energy (1/N) sum_sigma sum_ij T_ij (delta_ij - G_ji).
+__global__ __launch_bounds__(NT) void measure_kernel(KArgs a, dqmc_obs* obs, double* green) {
+  const int chain = blockIdx.x, tid = threadIdx.x;
+  const int n = a.n, np = a.np;
+  char* cb = a.base + (size_t)chain * a.stride;
+  const ChainStats* st = (const ChainStats*)(cb + a.o_stats);
+  const double* G64 = (const double*)(cb + a.o_G64);
+  const double* Gu = G64;
+  const double* Gd = G64 + (size_t)np * np;
+  __shared__ double red[3][NW];
+  double docc = 0, dens = 0, kin = 0;
+  for (int i = tid; i < n; i += NT) {
+    double gu = Gu[i * np + i], gd = Gd[i * np + i];
+    docc += (1.0 - gu) * (1.0 - gd);
+    dens += 2.0 - gu - gd;
+  }
+  for (int e = tid; e < n * n; e += NT) {
+    int i = e / n, j = e - i * n;
+    double t = a.Tm[i * np + j];
+    if (t != 0.0) kin += t * (2.0 * (i == j ? 1.0 : 0.0) - Gu[j * np + i] - Gd[j * np + i]);
+  }
+  docc = wave_sum(docc);
+  dens = wave_sum(dens);
+  kin = wave_sum(kin);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = docc;
+    red[1][tid >> 6] = dens;
+    red[2][tid >> 6] = kin;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int w = 0; w < NW; ++w) { s0 += red[0][w]; s1 += red[1][w]; s2 += red[2][w]; }
+    dqmc_obs o;
+    o.double_occ = s0 / n;
+    o.density = s1 / n;
+    o.kinetic = s2 / n;
+    o.logdet_up = st->logdet[0];
+    o.logdet_dn = st->logdet[1];
+    o.max_drift = st->max_drift;
+    o.max_logdet_err = st->max_logdet_err;
+    o.attempted = st->attempted;
+    o.accepted = st->accepted;
+    o.near_ties = st->near_ties;
+    o.sweeps_done = st->sweeps_done;
+    o.flags = st->flags;
+    o.reserved = 0;
+    obs[chain] = o;
+  }
+  if (green) {
+    double* out = green + (size_t)chain * 2 * n * n;
+    for (int e = tid; e < 2 * n * n; e += NT) {
+      int sp = e / (n * n), i = (e / n) % n, j = e % n;
+      out[e] = G64[(size_t)sp * np * np + i * np + j];
+    }
+  }
+}
+
+__global__ void get_fields_kernel(KArgs a, int8_t* out) {
+  const int chain = blockIdx.x;
+  const int8_t* f = (const int8_t*)(a.base + (size_t)chain * a.stride + a.o_fields);
+  for (int e = threadIdx.x; e < a.L * a.n; e += blockDim.x) {
+    int l = e / a.n, i = e - l * a.n;
+    out[(size_t)chain * a.L * a.n + e] = f[l * a.np + i];
+  }
+}
+
+__global__ void copy_propagators_kernel(KArgs a) {
+  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < 2 * a.n * a.n; e += blockDim.x * gridDim.x) {
+    int w = e / (a.n * a.n), i = (e / a.n) % a.n, j = e % a.n;
+    a.out[e] = (w ? a.expKinv : a.expK)[i * a.np + j];
+  }
+}
+
+__global__ void philox_kernel(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
+                              uint64_t c3, int n_blocks, uint64_t* out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_blocks) return;
+  u64x4 w = philox4x64_10(u64x4{c0 + (uint64_t)j, c1, c2, c3}, k0, k1);
+  out[4 * j + 0] = w.x0;
+  out[4 * j + 1] = w.x1;
+  out[4 * j + 2] = w.x2;
+  out[4 * j + 3] = w.x3;
+}
+
+// One wave: C = A B for a 16x4 A and a 4x16 B, written through the layout the library assumes.
+__global__ void mfma_probe_kernel(const double* a64, const double* b64, double* out64,
+                                  const float* a32, const float* b32, float* out32) {
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc = {0, 0, 0, 0};
+  acc = mfma(a64[li * 4 + lk], b64[lk * 16 + li], acc);
+  f4 acc32 = {0, 0, 0, 0};
+  acc32 = mfma(a32[li * 4 + lk], b32[lk * 16 + li], acc32);
+  for (int v = 0; v < 4; ++v) {
+    out64[out_row<double>(v, lane) * 16 + li] = acc[v];
+    out32[out_row<float>(v, lane) * 16 + li] = acc32[v];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ the handle
+struct dqmc_batch {
+  int n, np, L, stab, J, K, n_chains, precision;
+  bool small;
+  size_t lds_bytes;
+  KArgs args;   // base arguments (op fields filled per call)
+  char* ws;
+  size_t ws_bytes;
+};
+
+namespace {
+
+struct Layout {
+  int n, np, L, stab, J, K, precision;
+  bool small;
+  size_t lds_bytes;
+  // constants region (offsets from the workspace base)
+  size_t c_expK, c_expKinv, c_expK32, c_expKinv32, c_T, c_eye, c_ones, c_A, c_E0, c_E1, c_seeds,
+      c_err, c_end;
+  // per chain
+  size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, stride;
+};
+
+int max_lds_per_block() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      cached = v;
+    else
+      cached = 160 * 1024;
+  }
+  return cached;
+}
+
+dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool query_device) {
+  if (!m) return fail(DQMC_EINVAL, "model is NULL");
+  if (m->n_sites < 1 || m->n_sites > 2048) return fail(DQMC_EINVAL, "n_sites must be in [1, 2048]");
+  if (m->n_slices < 1) return fail(DQMC_EINVAL, "n_slices must be >= 1");
+  if (!(m->dtau > 0.0) || !(m->U >= 0.0) || !std::isfinite(m->mu))
+    return fail(DQMC_EINVAL, "need dtau > 0, U >= 0, finite mu");
+  if (m->stab_every < 1) return fail(DQMC_EINVAL, "stab_every must be >= 1");
+  if (m->precision != DQMC_FP64 && m->precision != DQMC_FP32_WRAP)
+    return fail(DQMC_EINVAL, "unknown precision");
+  if (m->refresh_every < 0 || m->delay_rank < 0) return fail(DQMC_EINVAL, "negative refresh/delay");
+  if (n_chains < 0) return fail(DQMC_EINVAL, "n_chains must be >= 0");
+  Layout L{};
+  L.n = m->n_sites;
+  L.np = (L.n + 15) & ~15;
+  L.L = m->n_slices;
+  L.precision = m->precision;
+  int stab = m->stab_every;
+  if (m->precision == DQMC_FP32_WRAP && m->refresh_every > 0) stab = std::min(stab, m->refresh_every);
+  L.stab = std::min(stab, L.L);
+  L.J = (L.L + L.stab - 1) / L.stab;
+  const size_t wts = m->precision == DQMC_FP32_WRAP ? sizeof(float) : sizeof(double);
+  const size_t nn = (size_t)L.np * L.np;
+  // delay rank: multiple of 4; the small variant stores the panels in its work matrices
+  int kreq = m->delay_rank > 0 ? m->delay_rank : 16;
+  kreq = (kreq + 3) & ~3;
+  const int lds_limit = query_device ? max_lds_per_block() : 160 * 1024;
+  auto small_bytes = [&](int K) {
+    return (wts == 8 ? lds_mat_bytes<double>(L.np) : lds_mat_bytes<float>(L.np)) +
+           lds_vec_doubles(L.np, K) * sizeof(double);
+  };
+  int k_small = std::min(kreq, 16);
+  k_small = std::min(k_small, (int)(wts == 8 ? L.np / 2 : L.np));
+  k_small = std::max(4, k_small & ~3);
+  L.small = small_bytes(k_small) <= (size_t)lds_limit;
+  if (L.small) {
+    L.K = k_small;
+    L.lds_bytes = small_bytes(L.K);
+  } else {
+    L.K = std::max(4, std::min(kreq, 32));
+    L.lds_bytes = lds_vec_doubles(L.np, L.K) * sizeof(double);
+    if (L.lds_bytes > (size_t)lds_limit) return fail(DQMC_EINVAL, "n_sites too large for LDS vectors");
+  }
+  // constants
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.c_expK = take(nn * 8);
+  L.c_expKinv = take(nn * 8);
+  L.c_expK32 = take(nn * 4);
+  L.c_expKinv32 = take(nn * 4);
+  L.c_T = take(nn * 8);
+  L.c_eye = take(nn * 8);
+  L.c_ones = take((size_t)L.np * 8);
+  L.c_A = take(nn * 8);
+  L.c_E0 = take(nn * 8);
+  L.c_E1 = take(nn * 8);
+  L.c_seeds = take((size_t)std::max(n_chains, 1) * 8);
+  L.c_err = take(256);
+  L.c_end = off;
+  // chain
+  size_t co = 0;
+  auto ctake = [&](size_t bytes) { size_t o = co; co = align256(co + bytes); return o; };
+  L.o_stats = ctake(sizeof(ChainStats));
+  L.o_fields = ctake((size_t)L.L * L.np);
+  L.o_G64 = ctake(2 * nn * 8);
+  L.o_stack = ctake(2 * (size_t)L.J * (2 * nn + L.np) * 8);
+  L.o_left = ctake(2 * (3 * nn + L.np) * 8);
+  if (!L.small) {
+    L.o_Gw = ctake(2 * nn * wts);
+    L.o_work = ctake(2 * nn * 8);
+    L.o_xy = ctake(4 * (size_t)L.np * L.K * wts);
+  } else {
+    L.o_Gw = L.o_work = L.o_xy = 0;
+  }
+  L.stride = align256(co);
+  *out = L;
+  return DQMC_OK;
+}
+
+void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KArgs* a) {
+  std::memset(a, 0, sizeof(*a));
+  a->n = L.n; a->np = L.np; a->L = L.L; a->stab = L.stab; a->J = L.J; a->K = L.K;
+  a->n_chains = n_chains;
+  const double nu = std::acosh(std::exp(0.5 * m->U * m->dtau));
+  a->nu = nu;
+  a->ev[0] = std::exp(nu);
+  a->ev[1] = std::exp(-nu);
+  a->dup[0] = std::exp(2.0 * nu) - 1.0;    // s = -1: e^{-2 nu s} - 1
+  a->dup[1] = std::exp(-2.0 * nu) - 1.0;   // s = +1
+  a->ddn[0] = std::exp(-2.0 * nu) - 1.0;   // s = -1: e^{+2 nu s} - 1
+  a->ddn[1] = std::exp(2.0 * nu) - 1.0;
+  a->drift_limit = m->precision == DQMC_FP32_WRAP ? 1e-1 : 1e-3;
+  a->expK = (const double*)(ws + L.c_expK);
+  a->expKinv = (const double*)(ws + L.c_expKinv);
+  a->expK32 = (const float*)(ws + L.c_expK32);
+  a->expKinv32 = (const float*)(ws + L.c_expKinv32);
+  a->Tm = (const double*)(ws + L.c_T);
+  a->eye = (const double*)(ws + L.c_eye);
+  a->ones = (const double*)(ws + L.c_ones);
+  a->err = (int*)(ws + L.c_err);
+  a->base = ws + L.c_end;
+  a->stride = L.stride;
+  a->o_fields = L.o_fields; a->o_G64 = L.o_G64; a->o_Gw = L.o_Gw; a->o_stack = L.o_stack;
+  a->o_left = L.o_left; a->o_work = L.o_work; a->o_xy = L.o_xy; a->o_stats = L.o_stats;
+}
+
+template <typename WT, bool SMALL>
+dqmc_status launch_chain(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
+  auto kern = chain_kernel<WT, SMALL>;
+  if (b->lds_bytes > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)b->lds_bytes));
+  hipLaunchKernelGGL(kern, dim3(b->n_chains), dim3(NT), b->lds_bytes, s, a);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status launch(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
+  if (b->n_chains == 0) return DQMC_OK;
+  const bool f32 = b->precision == DQMC_FP32_WRAP;
+  if (f32) return b->small ? launch_chain<float, true>(b, a, s) : launch_chain<float, false>(b, a, s);
+  return b->small ? launch_chain<double, true>(b, a, s) : launch_chain<double, false>(b, a, s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* dqmc_last_error(void) { return g_err.c_str(); }
+
+size_t dqmc_chain_bytes(const dqmc_model* m) {
+  Layout L;
+  if (make_layout(m, 1, &L, false) != DQMC_OK) return 0;
+  return L.stride;
+}
+
+size_t dqmc_workspace_bytes(const dqmc_model* m, int32_t n_chains) {
+  Layout L;
+  if (make_layout(m, n_chains, &L, false) != DQMC_OK) return 0;
+  return L.c_end + (size_t)n_chains * L.stride;
+}
+
+dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_chains,
+                             const int8_t* fields, const uint64_t* seeds, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  if (!out) return fail(DQMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  dqmc_status st = make_layout(m, n_chains, &L, true);
+  if (st != DQMC_OK) return st;
+  if (!m->hopping) return fail(DQMC_EINVAL, "hopping is NULL");
+  if (n_chains > 0 && !seeds) return fail(DQMC_EINVAL, "seeds is NULL");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(DQMC_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = L.c_end + (size_t)n_chains * L.stride;
+  if (ws_bytes < need) return fail(DQMC_ENOMEM, "workspace too small: need " + std::to_string(need));
+  for (int i = 0; i < L.n; ++i)
+    for (int j = 0; j < L.n; ++j) {
+      double t = m->hopping[i * L.n + j];
+      if (!std::isfinite(t) || t != m->hopping[j * L.n + i])
+        return fail(DQMC_EINVAL, "hopping must be finite and symmetric");
+    }
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  // padded hopping matrix and seeds to the device
+  std::vector<double> Tp((size_t)L.np * L.np, 0.0);
+  double norm1 = 0.0;
+  for (int j = 0; j < L.n; ++j) {
+    double col = 0.0;
+    for (int i = 0; i < L.n; ++i) {
+      Tp[(size_t)i * L.np + j] = m->hopping[i * L.n + j];
+      col += std::fabs(m->dtau * (m->hopping[i * L.n + j] - (i == j ? m->mu : 0.0)));
+    }
+    norm1 = std::max(norm1, col);
+  }
+  int sq = 0;
+  while (std::ldexp(norm1, -sq) > 0.5) ++sq;
+  HIP_TRY(hipMemcpyAsync(ws + L.c_T, Tp.data(), Tp.size() * 8, hipMemcpyHostToDevice, s));
+  if (n_chains > 0)
+    HIP_TRY(hipMemcpyAsync(ws + L.c_seeds, seeds, (size_t)n_chains * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(constants_kernel, dim3(1), dim3(NT), 0, s, L.n, L.np, m->dtau, m->mu, sq,
+                     (const double*)(ws + L.c_T), (double*)(ws + L.c_A), (double*)(ws + L.c_E0),
+                     (double*)(ws + L.c_E1), (double*)(ws + L.c_expK), (double*)(ws + L.c_expKinv),
+                     (float*)(ws + L.c_expK32), (float*)(ws + L.c_expKinv32),
+                     (double*)(ws + L.c_eye), (double*)(ws + L.c_ones), (int*)(ws + L.c_err));
+  HIP_TRY(hipGetLastError());
+  dqmc_batch* b = new (std::nothrow) dqmc_batch;
+  if (!b) return fail(DQMC_EDEVICE, "host allocation failed");
+  b->n = L.n; b->np = L.np; b->L = L.L; b->stab = L.stab; b->J = L.J; b->K = L.K;
+  b->n_chains = n_chains; b->precision = L.precision; b->small = L.small; b->lds_bytes = L.lds_bytes;
+  b->ws = ws; b->ws_bytes = ws_bytes;
+  fill_args(L, m, ws, n_chains, &b->args);
+  KArgs a = b->args;
+  a.op = OP_INIT;
+  a.gen_fields = fields ? 0 : 1;
+  a.fields_in = fields;
+  a.seeds = (const uint64_t*)(ws + L.c_seeds);
+  st = launch(b, a, s);
+  if (st != DQMC_OK) { delete b; return st; }
+  int err = 0;
+  hipError_t e1 = hipMemcpyAsync(&err, ws + L.c_err, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s) : e1;
+  if (e2 != hipSuccess) {
+    delete b;
+    return fail(DQMC_EDEVICE, std::string("init: ") + hipGetErrorString(e2));
+  }
+  if (err) {
+    delete b;
+    return fail(DQMC_EINVAL, "fields must be +1 or -1");
+  }
+  *out = b;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_sweep(dqmc_batch* b, int32_t n_sweeps, void* stream) {
+  if (!b) return fail(DQMC_EINVAL, "batch is NULL");
+  if (n_sweeps < 0) return fail(DQMC_EINVAL, "n_sweeps must be >= 0");
+  if (n_sweeps == 0) return DQMC_OK;
+  KArgs a = b->args;
+  a.op = OP_SWEEP;
+  a.n_sweeps = n_sweeps;
+  return launch(b, a, (hipStream_t)stream);
+}
+
+dqmc_status dqmc_sweep_multi(dqmc_batch* const* bs, const int32_t* n_sweeps, int32_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!bs || !n_sweeps))) return fail(DQMC_EINVAL, "bad batch list");
+  for (int i = 0; i < n; ++i)
+    if (!bs[i] || n_sweeps[i] < 0) return fail(DQMC_EINVAL, "bad batch entry");
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 1) return dqmc_sweep(bs[0], n_sweeps[0], stream);
+  // fork: every batch on its own stream after an event on the caller's stream, then join
+  std::vector<hipStream_t> side(n, nullptr);
+  std::vector<hipEvent_t> done(n, nullptr);
+  hipEvent_t fork = nullptr;
+  dqmc_status st = DQMC_OK;
+  auto cleanup = [&]() {
+    for (int i = 0; i < n; ++i) {
+      if (done[i]) hipEventDestroy(done[i]);
+      if (side[i]) hipStreamDestroy(side[i]);
+    }
+    if (fork) hipEventDestroy(fork);
+  };
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(fork, s) != hipSuccess) {
+    cleanup();
+    return fail(DQMC_EDEVICE, "sweep_multi: fork event");
+  }
+  for (int i = 0; i < n && st == DQMC_OK; ++i) {
+    if (hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&done[i], hipEventDisableTiming) != hipSuccess ||
+        hipStreamWaitEvent(side[i], fork, 0) != hipSuccess) {
+      st = fail(DQMC_EDEVICE, "sweep_multi: stream setup");
+      break;
+    }
+    st = dqmc_sweep(bs[i], n_sweeps[i], side[i]);
+    if (st == DQMC_OK && (hipEventRecord(done[i], side[i]) != hipSuccess ||
+                          hipStreamWaitEvent(s, done[i], 0) != hipSuccess))
+      st = fail(DQMC_EDEVICE, "sweep_multi: join");
+  }
+  cleanup();   // destroying a stream with pending work is deferred by the runtime
+  return st;
+}
+
+dqmc_status dqmc_measure(dqmc_batch* b, dqmc_obs* obs, double* green, void* stream) {
+  if (!b || !obs) return fail(DQMC_EINVAL, "batch/obs is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (b->n_chains == 0) return DQMC_OK;
+  hipLaunchKernelGGL(measure_kernel, dim3(b->n_chains), dim3(NT), 0, s, b->args, obs, green);
+  HIP_TRY(hipGetLastError());
+  std::vector<dqmc_obs> h(b->n_chains);
+  HIP_TRY(hipMemcpyAsync(h.data(), obs, h.size() * sizeof(dqmc_obs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (const dqmc_obs& o : h)
+    if (o.flags) return fail(DQMC_ENUMERIC, "a chain raised a numerical flag");
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_fields(dqmc_batch* b, int8_t* out, void* stream) {
+  if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
+  if (b->n_chains == 0) return DQMC_OK;
+  hipLaunchKernelGGL(get_fields_kernel, dim3(b->n_chains), dim3(256), 0, (hipStream_t)stream,
+                     b->args, out);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_destroy(dqmc_batch* b) {
+  delete b;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int32_t* lds_bytes,
+                            int32_t* variant) {
+  if (!b) return fail(DQMC_EINVAL, "batch is NULL");
+  if (k) *k = b->K;
+  if (stab) *stab = b->stab;
+  if (lds_bytes) *lds_bytes = (int32_t)b->lds_bytes;
+  if (variant) *variant = b->small ? 0 : 1;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_debug_green(dqmc_batch* b, int32_t slice, int32_t n_wraps, double* out, void* stream) {
+  if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
+  if (slice < 0 || n_wraps < 0 || slice + n_wraps > b->L) return fail(DQMC_EINVAL, "slice range");
+  KArgs a = b->args;
+  a.op = OP_DEBUG_GREEN;
+  a.slice = slice;
+  a.n_wraps = n_wraps;
+  a.out = out;
+  return launch(b, a, (hipStream_t)stream);
+}
+
+dqmc_status dqmc_debug_ratios(dqmc_batch* b, int32_t slice, double* out, void* stream) {
+  if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
+  if (slice < 1 || slice > b->L) return fail(DQMC_EINVAL, "slice must be in [1, n_slices]");
+  KArgs a = b->args;
+  a.op = OP_DEBUG_RATIOS;
+  a.slice = slice;
+  a.out = out;
+  return launch(b, a, (hipStream_t)stream);
+}
+
+dqmc_status dqmc_debug_propagators(dqmc_batch* b, double* out, void* stream) {
+  if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
+  KArgs a = b->args;
+  a.out = out;
+  hipLaunchKernelGGL(copy_propagators_kernel, dim3(16), dim3(256), 0, (hipStream_t)stream, a);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_debug_philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
+                              uint64_t c3, int32_t n_blocks, uint64_t* out, void* stream) {
+  if (!out || n_blocks < 0) return fail(DQMC_EINVAL, "bad philox arguments");
+  if (n_blocks == 0) return DQMC_OK;
+  hipLaunchKernelGGL(philox_kernel, dim3((n_blocks + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     k0, k1, c0, c1, c2, c3, n_blocks, out);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_debug_mfma(const double* a64, const double* b64, double* out64, const float* a32,
+                            const float* b32, float* out32, void* stream) {
+  if (!a64 || !b64 || !out64 || !a32 || !b32 || !out32) return fail(DQMC_EINVAL, "NULL argument");
+  hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, a64, b64, out64,
+                     a32, b32, out32);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1006 @@
+// Device side of the batched DQMC sweep (gfx950 / CDNA4).
+//
+// One workgroup of 256 threads (4 wave64s) owns one Markov chain for the whole call: the
+// kernels are persistent over slices and sweeps, and all per-chain state is resident either in
+// LDS (Green's functions and two work matrices, "small" variant) or in the chain's slice of the
+// caller's workspace ("large" variant).  Dense products run on the matrix cores through
+// 16x16x4 MFMA tiles (FP64, or FP32 for the wraps and delayed updates in FP32-wrap precision);
+// the latency-bound parts (the sequential Metropolis loop, pivot searches) use wave-synchronous
+// LDS traffic and wavefront reductions.
+//
+// Notation of the paper's supplement, section I.2: L slices of width dtau, HS field s_{i,l}=+-1,
+// cosh(nu) = e^{U dtau/2}, B^sigma_l = e^{sigma nu Diag(s_l)} e^{-dtau T}, weight
+// prod_sigma det(I + B^sigma(L,0)).  Everything beyond that (Green's function, wrap, ratio,
+// Sherman-Morrison/submatrix updates, UDT stabilisation) is derived in the comments below.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dqmc {
+
+constexpr int NT = 256;        // threads per workgroup (one chain)
+constexpr int NW = NT / 64;    // wavefronts per workgroup
+
+enum { OP_INIT = 0, OP_SWEEP = 1, OP_DEBUG_GREEN = 2, OP_DEBUG_RATIOS = 3 };
+enum { FLAG_NONFINITE = 1, FLAG_NEGATIVE = 2, FLAG_DRIFT = 4, FLAG_SINGULAR = 8 };
+
+// Per-chain bookkeeping kept in the workspace.
+struct ChainStats {
+  uint64_t seed;
+  int64_t sweeps_done, attempted, accepted, near_ties;
+  double max_drift, max_logdet_err;
+  double logdet[2];
+  int32_t flags, pad;
+};
+
+// Everything a kernel launch needs (passed by value).
+struct KArgs {
+  int n, np, L, stab, J, K, n_chains, op, slice, n_wraps, n_sweeps, gen_fields;
+  double nu, drift_limit;
+  double ev[2];     // e^{+nu}, e^{-nu}
+  double dup[2];    // Delta^up(s)   = e^{-2 nu s} - 1 for s = -1 (index 0), s = +1 (index 1)
+  double ddn[2];    // Delta^down(s) = e^{+2 nu s} - 1
+  const double* expK;
+  const double* expKinv;
+  const float* expK32;
+  const float* expKinv32;
+  const double* Tm;     // hopping (np x np, zero padded), for the kinetic energy
+  const double* eye;    // n x n identity zero-padded to np x np
+  const double* ones;   // np ones
+  int* err;             // device error word (field validation)
+  const int8_t* fields_in;
+  const uint64_t* seeds;
+  char* base;
+  size_t stride;        // bytes per chain
+  size_t o_fields, o_G64, o_Gw, o_stack, o_left, o_work, o_xy, o_stats;
+  double* out;
+};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4 type; };
+template <> struct acc4<float> { typedef f4 type; };
+
+// acc += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and B[l/16][l%16].
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of output register v held by lane l (column = l % 16).  The FP64 instruction returns four
+// row groups of one row each (rows v*4 + l/16); the FP32 one a single group of four rows
+// (rows 4*(l/16) + v).  Checked on the device by dqmc_debug_mfma.
+template <typename T> __device__ __forceinline__ int out_row(int v, int lane);
+template <> __device__ __forceinline__ int out_row<double>(int v, int lane) { return 4 * v + (lane >> 4); }
+template <> __device__ __forceinline__ int out_row<float>(int v, int lane) { return 4 * (lane >> 4) + v; }
+
+// Compiler and LDS ordering point for wave-synchronous code (one wave, no s_barrier).
+__device__ __forceinline__ void wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// --------------------------------------------------------------------------------- GEMM tiles
+// nb independent products C_b(i,j) = sum_{k<K} A_b(i,k) B_b(k,j), i < M, j < Nc (multiples of
+// 16), K a multiple of 4; A_b(i,k) = A_b[i*sai + k*sak], B_b(k,j) = B_b[k*sbk + j*sbj].
+// The 16x16 output tiles of all nb products are dealt round-robin to the four wavefronts;
+// epi(b, i, j, value) is called exactly once per output element, by the lane owning it.
+template <typename T, typename Epi>
+__device__ __forceinline__ void wg_gemm(int nb, int M, int Nc, int K, const T* A0, const T* A1,
+                                        int sai, int sak, const T* B0, const T* B1, int sbk,
+                                        int sbj, Epi epi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tn = Nc >> 4, tpb = (M >> 4) * tn;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < nb * tpb; t += NW) {
+    const int b = t / tpb, tt = t - b * tpb;
+    const int ti = tt / tn, tj = tt - ti * tn;
+    const T* a = (b ? A1 : A0) + (ti * 16 + li) * sai + lk * sak;
+    const T* bb = (b ? B1 : B0) + lk * sbk + (tj * 16 + li) * sbj;
+    typename acc4<T>::type acc = {0, 0, 0, 0};
+    int k = 0;
+    for (; k + 16 <= K; k += 16) {
+      T a0 = a[(k + 0) * sak], a1 = a[(k + 4) * sak], a2 = a[(k + 8) * sak], a3 = a[(k + 12) * sak];
+      T b0 = bb[(k + 0) * sbk], b1 = bb[(k + 4) * sbk], b2 = bb[(k + 8) * sbk], b3 = bb[(k + 12) * sbk];
+      acc = mfma(a0, b0, acc);
+      acc = mfma(a1, b1, acc);
+      acc = mfma(a2, b2, acc);
+      acc = mfma(a3, b3, acc);
+    }
+    for (; k < K; k += 4) acc = mfma(a[k * sak], bb[k * sbk], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) epi(b, ti * 16 + out_row<T>(v, lane), tj * 16 + li, acc[v]);
+  }
+}
+
+// ------------------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+// Sum over the 4 consecutive lanes of a column group.
+__device__ __forceinline__ double group4_sum(double x) {
+  x += __shfl_xor(x, 1);
+  x += __shfl_xor(x, 2);
+  return x;
+}
+
+// LDS scratch the reductions use: red[2][NW] doubles and redi[2][NW] ints, double-buffered by
+// the parity of the call so that one barrier per reduction suffices.
+struct Red {
+  double* v;
+  int* i;
+  int parity;
+};
+
+// Largest value over the workgroup (every thread contributes x); returns it to all threads.
+__device__ __forceinline__ double wg_max(double x, Red& r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  x = wave_max(x);
+  double* buf = r.v + r.parity * NW;
+  r.parity ^= 1;
+  if (lane == 0) buf[wave] = x;
+  __syncthreads();
+  double m = buf[0];
+  for (int w = 1; w < NW; ++w) m = fmax(m, buf[w]);
+  return m;
+}
+
+// Index of the largest key over the workgroup (ties -> smallest index); every thread offers
+// one (key, idx) pair, idx < 0 meaning "no candidate".  Returns the winner to all threads.
+__device__ __forceinline__ int wg_argmax(double key, int idx, Red& r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (idx < 0) key = -1.0;
+  for (int o = 32; o > 0; o >>= 1) {
+    double k2 = __shfl_xor(key, o);
+    int i2 = __shfl_xor(idx, o);
+    bool take = (i2 >= 0) && (idx < 0 || k2 > key || (k2 == key && i2 < idx));
+    if (take) { key = k2; idx = i2; }
+  }
+  double* bv = r.v + r.parity * NW;
+  int* bi = r.i + r.parity * NW;
+  r.parity ^= 1;
+  if (lane == 0) { bv[wave] = key; bi[wave] = idx; }
+  __syncthreads();
+  double bk = bv[0];
+  int best = bi[0];
+  for (int w = 1; w < NW; ++w) {
+    double k2 = bv[w];
+    int i2 = bi[w];
+    if (i2 >= 0 && (best < 0 || k2 > bk || (k2 == bk && i2 < best))) { bk = k2; best = i2; }
+  }
+  return best;
+}
+
+// ------------------------------------------------------------------------------ Philox
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128 products on
+// a four-word counter, key bumped by the Weyl constants between rounds.
+struct u64x4 { uint64_t x0, x1, x2, x3; };
+__device__ __forceinline__ u64x4 philox4x64_10(u64x4 c, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint64_t hi0 = __umul64hi(M0, c.x0), lo0 = M0 * c.x0;
+    uint64_t hi1 = __umul64hi(M1, c.x2), lo1 = M1 * c.x2;
+    c = u64x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
+  }
+  return c;
+}
+// Acceptance uniform of (global sweep, 0-based slice, site): counter (site, slice, sweep, 1),
+// key (seed, 0), first word, top 53 bits.
+__device__ __forceinline__ double accept_uniform(uint64_t seed, int64_t sweep, int slice, int site) {
+  u64x4 w = philox4x64_10(u64x4{(uint64_t)site, (uint64_t)slice, (uint64_t)sweep, 1ull}, seed, 0ull);
+  return (double)(w.x0 >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------------------ chain context
+template <typename WT>
+struct Ctx {
+  const KArgs* a;
+  int n, np, L, stab, J, K;
+  ChainStats* st;
+  int8_t* f;          // fields [L][np]
+  double* G64;        // [2][np*np] fresh G(0) record
+  WT* G[2];           // working Green's functions (LDS or global)
+  double* w1;         // work matrices (LDS or global), np*np doubles each
+  double* w2;
+  WT* xy;             // delayed-update panels: X_up, Y_up, X_dn, Y_dn (np*K each)
+  double* stack;      // right UDT stack [2][J][U, T, d]
+  double* left;       // left UDT [2][U, T0, T1, d]
+  // LDS vectors
+  double *vd, *bt, *nrm, *dtmp, *sr, *sc;   // sr/sc: [2][np] row/column scale factors
+  int* ordv;          // [np] pivot order / used marks
+  int* rank;          // [np]
+  double *gb, *xb, *yb;   // [2][K*K] each
+  double *cfu, *cfd, *ublk;  // [K]
+  int *site, *sblk, *cnt;   // [K], [K], [4]
+  double* misc;       // [16]
+  Red red;
+};
+
+template <typename WT>
+__device__ __forceinline__ const WT* kexp(const KArgs& a);
+template <> __device__ __forceinline__ const double* kexp<double>(const KArgs& a) { return a.expK; }
+template <> __device__ __forceinline__ const float* kexp<float>(const KArgs& a) { return a.expK32; }
+template <typename WT>
+__device__ __forceinline__ const WT* kexpinv(const KArgs& a);
+template <> __device__ __forceinline__ const double* kexpinv<double>(const KArgs& a) { return a.expKinv; }
+template <> __device__ __forceinline__ const float* kexpinv<float>(const KArgs& a) { return a.expKinv32; }
+
+// Bytes of LDS the vector area needs (both variants) and the matrix area (small variant).
+__host__ __device__ inline size_t lds_vec_doubles(int np, int K) {
+  return 2 * NW + NW + 6 * (size_t)np + 4 * (size_t)np + 6 * (size_t)K * K + 3 * (size_t)K +
+         (3 * (size_t)K + 8) / 2 + 1 + 16 + (2 * (size_t)np + 1) / 2 + 8;
+}
+template <typename WT>
+__host__ __device__ inline size_t lds_mat_bytes(int np) {
+  return 2 * (size_t)np * np * sizeof(WT) + 2 * (size_t)np * np * sizeof(double);
+}
+
+template <typename WT, bool SMALL>
+__device__ inline Ctx<WT> make_ctx(const KArgs& a, int chain, double* lds) {
+  Ctx<WT> c;
+  c.a = &a;
+  c.n = a.n; c.np = a.np; c.L = a.L; c.stab = a.stab; c.J = a.J; c.K = a.K;
+  const int np = a.np, K = a.K;
+  const size_t nn = (size_t)np * np;
+  char* cb = a.base + (size_t)chain * a.stride;
+  c.st = (ChainStats*)(cb + a.o_stats);
+  c.f = (int8_t*)(cb + a.o_fields);
+  c.G64 = (double*)(cb + a.o_G64);
+  c.stack = (double*)(cb + a.o_stack);
+  c.left = (double*)(cb + a.o_left);
+  double* p = lds;
+  if (SMALL) {
+    WT* g = (WT*)p;
+    c.G[0] = g;
+    c.G[1] = g + nn;
+    p = (double*)(g + 2 * nn);
+    c.w1 = p;
+    c.w2 = p + nn;
+    p += 2 * nn;
+    c.xy = (WT*)c.w1;   // the panels reuse the work matrices during the Metropolis loop
+  } else {
+    WT* g = (WT*)(cb + a.o_Gw);
+    c.G[0] = g;
+    c.G[1] = g + nn;
+    c.w1 = (double*)(cb + a.o_work);
+    c.w2 = c.w1 + nn;
+    c.xy = (WT*)(cb + a.o_xy);
+  }
+  c.red.v = p; p += 2 * NW;
+  c.misc = p; p += 16;
+  c.vd = p; p += np;
+  c.bt = p; p += np;
+  c.nrm = p; p += np;
+  c.dtmp = p; p += np;
+  c.sr = p; p += 2 * np;
+  c.sc = p; p += 2 * np;
+  c.gb = p; p += 2 * (size_t)K * K;
+  c.xb = p; p += 2 * (size_t)K * K;
+  c.yb = p; p += 2 * (size_t)K * K;
+  c.cfu = p; p += K;
+  c.cfd = p; p += K;
+  c.ublk = p; p += K;
+  int* ip = (int*)p;
+  c.red.i = ip; ip += 2 * NW;
+  c.site = ip; ip += K;
+  c.sblk = ip; ip += K;
+  c.cnt = ip; ip += 4;
+  c.ordv = ip; ip += np;
+  c.rank = ip; ip += np;
+  c.red.parity = 0;
+  return c;
+}
+
+// ------------------------------------------------------------------------------ helpers
+// e^{sigma nu s} for s = +-1 (sigma = +1 for spin index 0, -1 for 1).
+__device__ __forceinline__ double vfac(const KArgs& a, int spin, int s) {
+  return ((s > 0) == (spin == 0)) ? a.ev[0] : a.ev[1];
+}
+
+// dst = U Diag(d) (n x n in np x np, zero padded), optionally with rows scaled by rs[].
+__device__ inline void form_ud(int np, const double* U, const double* d, const double* rs, double* dst) {
+  for (int e = threadIdx.x; e < np * np; e += NT) {
+    int i = e / np, j = e - i * np;
+    double v = U[e] * d[j];
+    if (rs) v *= rs[i];
+    dst[e] = v;
+  }
+}
+
+// Fill the row-scale vector sr[spin][i] = e^{sigma nu s_{l,i}} (1 on padding) for slice index
+// li (0-based) of the field, both spins, and its inverse into sc.
+template <typename WT>
+__device__ inline void slice_scales(Ctx<WT>& c, int li) {
+  const KArgs& a = *c.a;
+  for (int e = threadIdx.x; e < 2 * c.np; e += NT) {
+    int sp = e / c.np, i = e - sp * c.np;
+    double v = 1.0, w = 1.0;
+    if (i < c.n) {
+      int s = c.f[(size_t)li * c.np + i];
+      v = vfac(a, sp, s);
+      w = vfac(a, sp, -s);
+    }
+    c.sr[e] = v;
+    c.sc[e] = w;
+  }
+}
+
+// ------------------------------------------------------------------------------ QR / UDT
+// Column-pivoted Householder QR (Golub & Van Loan, Alg. 5.4.1) of the n x n leading block of
+// X (leading dimension np), with implicit pivoting: columns stay in place, ordv[j] is the
+// column chosen at step j, rank[c] the step at which column c was chosen.  On return row j of
+// column ordv[j'] (j <= j') holds R[j][j']; column ordv[j] below row j holds the Householder
+// vector v_j (v_j[j] in vd[j]) and bt[j] = beta_j = 2 / (v_j^T v_j).  Pivot = the remaining
+// column of largest norm over the remaining rows, recomputed exactly at every step.
+template <typename WT>
+__device__ void wg_qrp(Ctx<WT>& c, double* X) {
+  const int n = c.n, np = c.np, tid = threadIdx.x;
+  const int g = tid >> 2, q = tid & 3;
+  for (int k = tid; k < n; k += NT) c.rank[k] = -1;
+  for (int col = g; col < n; col += NT / 4) {
+    double s = 0;
+    for (int r = q; r < n; r += 4) { double x = X[r * np + col]; s += x * x; }
+    s = group4_sum(s);
+    if (q == 0) c.nrm[col] = s;
+  }
+  double alpha_prev = 0, v0_prev = 0, beta_prev = 0;
+  int p_prev = -1;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // publish the previous step's R diagonal and reflector (column p_prev is no longer read)
+    if (tid == 0 && p_prev >= 0) {
+      X[(j - 1) * np + p_prev] = alpha_prev;
+      c.vd[j - 1] = v0_prev;
+      c.bt[j - 1] = beta_prev;
+    }
+    // pivot: largest remaining column norm
+    double key = -1.0;
+    int idx = -1;
+    for (int k = tid; k < n; k += NT) {
+      if (c.rank[k] < 0) {
+        double v = c.nrm[k];
+        if (idx < 0 || v > key) { key = v; idx = k; }
+      }
+    }
+    const int p = wg_argmax(key, idx, c.red);
+    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; }
+    const double xj = X[j * np + p];
+    const double nx = sqrt(c.nrm[p]);
+    const double alpha = (xj >= 0.0) ? -nx : nx;
+    const double beta = (nx > 0.0) ? 1.0 / (alpha * (alpha - xj)) : 0.0;
+    const double v0 = xj - alpha;
+    // apply H_j = I - beta v v^T to every remaining column, recomputing its norm below row j
+    for (int k0 = 0; k0 < n; k0 += NT / 4) {
+      const int col = k0 + g;
+      const bool act = (col < n) && (col != p) && (c.rank[col] < 0);
+      if (!__builtin_expect(act, 1)) continue;
+      double w = 0;
+      for (int r = j + q; r < n; r += 4) {
+        double vr = (r == j) ? v0 : X[r * np + p];
+        w += vr * X[r * np + col];
+      }
+      w = group4_sum(w) * beta;
+      double s2 = 0;
+      for (int r = j + q; r < n; r += 4) {
+        double vr = (r == j) ? v0 : X[r * np + p];
+        double x = X[r * np + col] - w * vr;
+        X[r * np + col] = x;
+        if (r > j) s2 += x * x;
+      }
+      s2 = group4_sum(s2);
+      if (q == 0) c.nrm[col] = s2;
+    }
+    alpha_prev = alpha; v0_prev = v0; beta_prev = beta; p_prev = p;
+    __syncthreads();
+  }
+  if (tid == 0 && p_prev >= 0) {
+    X[(n - 1) * np + p_prev] = alpha_prev;
+    c.vd[n - 1] = v0_prev;
+    c.bt[n - 1] = beta_prev;
+  }
+  __syncthreads();
+}
+
+// After wg_qrp: U = Q S (columns in pivot order, S = sign(diag R)) into Ud (np x np, zero
+// padded), d_j = |R_jj| into dd (1 on padding), then X <- T' = D^{-1} S R P^T in original
+// column order (zero padded): T'[a][col] = s_a X[a][col] / d_a when rank[col] >= a.
+template <typename WT>
+__device__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* flags) {
+  const int n = c.n, np = c.np, tid = threadIdx.x;
+  const int g = tid >> 2, q = tid & 3;
+  // Q column jj = H_0 H_1 ... H_jj e_jj (later reflectors do not touch e_jj)
+  for (int jj = g; jj < np; jj += NT / 4) {
+    for (int r = q; r < np; r += 4) Ud[r * np + jj] = (r == jj && jj < n) ? 1.0 : 0.0;
+    if (jj >= n) continue;
+    for (int j = jj; j >= 0; --j) {
+      const int p = c.ordv[j];
+      double w = 0;
+      for (int r = j + q; r < n; r += 4) {
+        double vr = (r == j) ? c.vd[j] : X[r * np + p];
+        w += vr * Ud[r * np + jj];
+      }
+      w = group4_sum(w) * c.bt[j];
+      for (int r = j + q; r < n; r += 4) {
+        double vr = (r == j) ? c.vd[j] : X[r * np + p];
+        Ud[r * np + jj] -= w * vr;
+      }
+    }
+  }
+  __syncthreads();
+  // signs and scales
+  for (int jj = tid; jj < np; jj += NT) {
+    double dj = 1.0, sj = 1.0;
+    if (jj < n) {
+      double rjj = X[jj * np + c.ordv[jj]];
+      dj = fabs(rjj);
+      sj = (rjj < 0.0) ? -1.0 : 1.0;
+      if (!(dj > 0.0)) atomicOr(flags, FLAG_SINGULAR);
+    }
+    c.dtmp[jj] = sj;
+    dd[jj] = dj;
+  }
+  __syncthreads();
+  for (int e = tid; e < np * np; e += NT) {
+    int r = e / np, col = e - r * np;
+    if (col < n) Ud[e] *= c.dtmp[col];
+  }
+  for (int e = tid; e < np * np; e += NT) {
+    int aa = e / np, col = e - aa * np;
+    double v = 0.0;
+    if (aa < n && col < n && c.rank[col] >= aa) v = c.dtmp[aa] * X[e] / dd[aa];
+    X[e] = v;
+  }
+  __syncthreads();
+}
+
+// Multiply a chunk of slice propagators onto (Us, ds, Ts) and re-factorise:
+//   left  (right == false): product B_{hi} ... B_{lo+1} U D, B_l = V_l expK;
+//   right (right == true):  product B_{lo+1}^T ... B_{hi}^T U D, B_l^T = expK^T V_l;
+// then UDT of the result: Ud Diag(dd) (T' Ts) -> (Ud, dd, Td).  Ts may be the identity.
+// Work matrices w1/w2 are used; the result ends up in the destination buffers.
+template <typename WT>
+__device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const double* Us,
+                         const double* ds, const double* Ts, double* Ud, double* dd, double* Td) {
+  const KArgs& a = *c.a;
+  const int np = c.np, n = c.n;
+  double* cur = c.w1;
+  double* nxt = c.w2;
+  if (!right) {
+    form_ud(np, Us, ds, nullptr, cur);
+    __syncthreads();
+    for (int l = lo + 1; l <= hi; ++l) {
+      const int8_t* fl = c.f + (size_t)(l - 1) * np;
+      wg_gemm<double>(1, np, np, np, a.expK, a.expK, np, 1, cur, cur, np, 1,
+                      [&](int, int i, int j, double v) {
+                        double s = (i < n) ? vfac(a, spin, fl[i]) : 1.0;
+                        nxt[i * np + j] = s * v;
+                      });
+      __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
+    }
+  } else {
+    // X0 = V_hi U D
+    {
+      const int8_t* fl = c.f + (size_t)(hi - 1) * np;
+      for (int e = threadIdx.x; e < np * np; e += NT) {
+        int i = e / np, j = e - i * np;
+        double s = (i < n) ? vfac(a, spin, fl[i]) : 1.0;
+        cur[e] = s * Us[e] * ds[j];
+      }
+    }
+    __syncthreads();
+    for (int l = hi; l >= lo + 1; --l) {
+      const int8_t* fn = (l - 1 >= lo + 1) ? c.f + (size_t)(l - 2) * np : nullptr;
+      // expK^T as the A operand: A(i,k) = expK[k*np + i]
+      wg_gemm<double>(1, np, np, np, a.expK, a.expK, 1, np, cur, cur, np, 1,
+                      [&](int, int i, int j, double v) {
+                        double s = (fn && i < n) ? vfac(a, spin, fn[i]) : 1.0;
+                        nxt[i * np + j] = s * v;
+                      });
+      __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
+    }
+  }
+  wg_qrp(c, cur);
+  udt_finish(c, cur, Ud, dd, &c.st->flags);
+  // Td = T' Ts  (cur now holds T')
+  wg_gemm<double>(1, np, np, np, cur, cur, np, 1, Ts, Ts, np, 1,
+                  [&](int, int i, int j, double v) { Td[i * np + j] = v; });
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------ fresh G
+// Gauss-Jordan elimination with partial (implicit) row pivoting on M (n x n, leading dim np),
+// applied to the right-hand side Z (np columns).  On return w_dst = M^{-1} Z with its rows
+// scaled by rs[] (rs may be null), and the log|det M| is returned to all threads.
+template <typename WT>
+__device__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double* Z, double* dst, const double* rs) {
+  const int n = c.n, np = c.np, tid = threadIdx.x;
+  for (int k = tid; k < np; k += NT) c.rank[k] = -1;   // rank[row] = step at which row pivoted
+  __syncthreads();
+  double logabs = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double key = -1.0;
+    int idx = -1;
+    for (int r = tid; r < n; r += NT) {
+      if (c.rank[r] < 0) {
+        double v = fabs(M[r * np + j]);
+        if (idx < 0 || v > key) { key = v; idx = r; }
+      }
+    }
+    const int p = wg_argmax(key, idx, c.red);
+    const double piv = M[p * np + j];
+    logabs += log(fabs(piv));
+    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; c.dtmp[j] = piv; }
+    const double inv = 1.0 / piv;
+    // eliminate column j from every other row with the (unscaled) pivot row p
+    const int wM = n - j - 1;   // columns j+1 .. n-1 of M
+    const int tot = n * (wM + np);
+    for (int e = tid; e < tot; e += NT) {
+      int r = e / (wM + np), cc = e - r * (wM + np);
+      if (r == p) continue;
+      double fct = M[r * np + j] * inv;
+      if (fct == 0.0) continue;
+      if (cc < wM) {
+        int col = j + 1 + cc;
+        M[r * np + col] -= fct * M[p * np + col];
+      } else {
+        int col = cc - wM;
+        Z[r * np + col] -= fct * Z[p * np + col];
+      }
+    }
+    __syncthreads();
+  }
+  // x_j = Z[ordv[j]] / pivot_j, rows scaled by rs
+  for (int e = tid; e < np * np; e += NT) {
+    int j = e / np, col = e - j * np;
+    double v = 0.0;
+    if (j < n) {
+      v = Z[c.ordv[j] * np + col] / c.dtmp[j];
+      if (rs) v *= rs[j];
+    }
+    dst[e] = v;
+  }
+  __syncthreads();
+  return logabs;
+}
+
+// Fresh equal-time G^spin = [I + A B]^{-1} with A = UL DL TL (left, B(l,0)) and
+// B^T = UR DR TR (right, B(L,l)^T), by the two-sided split of the scales at 1:
+//   d = db ds, db = max(d,1), ds = min(d,1);
+//   I + A B = UL DLb [DLb^{-1} UL^T UR DRb^{-1} + DLs TL TR^T DRs] DRb UR^T = UL DLb M DRb UR^T
+//   G = UR DRb^{-1} M^{-1} DLb^{-1} UL^T,  log|det(I + A B)| = sum log DLb + sum log DRb + log|det M|.
+// The result replaces c.G[spin] (and G64 when g64 != null); returns the drift
+// max|G_old - G_new| and writes log|det| into *logdet.
+template <typename WT>
+__device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const double* dL,
+                              const double* TL, const double* UR, const double* dR,
+                              const double* TR, double* g64, double* logdet, bool drift) {
+  const int np = c.np, n = c.n, tid = threadIdx.x;
+  double* M = c.w1;
+  double* Z = c.w2;
+  // sr <- 1/DLb, sc <- 1/DRb for this call (slice scales are not live here)
+  double* iLb = c.sr;
+  double* iRb = c.sc;
+  for (int i = tid; i < np; i += NT) {
+    iLb[i] = 1.0 / fmax(dL[i], 1.0);
+    iRb[i] = 1.0 / fmax(dR[i], 1.0);
+  }
+  __syncthreads();
+  // M = DLb^{-1} (UL^T UR) DRb^{-1};  Z = DLb^{-1} UL^T
+  wg_gemm<double>(1, np, np, np, UL, UL, 1, np, UR, UR, np, 1,
+                  [&](int, int i, int j, double v) { M[i * np + j] = v * iLb[i] * iRb[j]; });
+  for (int e = tid; e < np * np; e += NT) {
+    int i = e / np, j = e - i * np;
+    Z[e] = UL[j * np + i] * iLb[i];
+  }
+  __syncthreads();
+  // M += DLs (TL TR^T) DRs
+  wg_gemm<double>(1, np, np, np, TL, TL, np, 1, TR, TR, 1, np, [&](int, int i, int j, double v) {
+    M[i * np + j] += fmin(dL[i], 1.0) * v * fmin(dR[j], 1.0);
+  });
+  __syncthreads();
+  // Z <- DRb^{-1} M^{-1} DLb^{-1} UL^T  (written into M's buffer)
+  double logm = wg_gauss_jordan(c, M, Z, M, iRb);
+  // G = UR (DRb^{-1} M^{-1} DLb^{-1} UL^T)
+  WT* G = c.G[spin];
+  double dmax = 0.0;
+  bool bad = false;
+  wg_gemm<double>(1, np, np, np, UR, UR, np, 1, M, M, np, 1, [&](int, int i, int j, double v) {
+    const int e = i * np + j;
+    if (drift) dmax = fmax(dmax, fabs((double)G[e] - v));
+    if (!(fabs(v) < 1e300)) bad = true;
+    G[e] = (WT)v;
+    if (g64) g64[e] = v;
+  });
+  if (bad) atomicOr(&c.st->flags, FLAG_NONFINITE);
+  double ld = logm;
+  {
+    double part = 0.0;
+    for (int i = tid; i < n; i += NT) part += log(fmax(dL[i], 1.0)) + log(fmax(dR[i], 1.0));
+    part = wave_sum(part);
+    double* buf = c.red.v + c.red.parity * NW;
+    c.red.parity ^= 1;
+    if ((tid & 63) == 0) buf[tid >> 6] = part;
+    __syncthreads();
+    for (int w = 0; w < NW; ++w) ld += buf[w];
+  }
+  *logdet = ld;
+  double dr = drift ? wg_max(dmax, c.red) : 0.0;
+  return dr;
+}
+
+// ------------------------------------------------------------------------------ wrap
+// G^sigma(l) = B_l G^sigma(l-1) B_l^{-1} = V_l expK G expKinv V_l^{-1} for both spins:
+// two MFMA products per spin in the working precision, the diagonal factors in the epilogue.
+template <typename WT>
+__device__ void wrap_both(Ctx<WT>& c, int l) {
+  const KArgs& a = *c.a;
+  const int np = c.np;
+  slice_scales(c, l - 1);
+  WT* t0 = (WT*)c.w1;
+  WT* t1 = (WT*)c.w2;
+  const WT* K1 = kexp<WT>(a);
+  const WT* K2 = kexpinv<WT>(a);
+  wg_gemm<WT>(2, np, np, np, K1, K1, np, 1, c.G[0], c.G[1], np, 1,
+              [&](int b, int i, int j, WT v) { (b ? t1 : t0)[i * np + j] = v; });
+  __syncthreads();
+  wg_gemm<WT>(2, np, np, np, t0, t1, np, 1, K2, K2, np, 1, [&](int b, int i, int j, WT v) {
+    c.G[b][i * np + j] = (WT)(c.sr[b * np + i] * (double)v * c.sc[b * np + j]);
+  });
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------ Metropolis
+// Single-flip Metropolis over the sites of slice l with submatrix (delayed) updates.
+//
+// Flipping s_{i,l} multiplies B^sigma_l from the left by (I + Delta^sigma e_i e_i^T),
+// Delta^sigma = e^{-2 sigma nu s_{i,l}} - 1, so with G = G(l) the weight ratio is
+// R = prod_sigma (1 + Delta^sigma (1 - G^sigma_ii)) and, on acceptance,
+// G' = G (I + Delta (I - G))^{-1} = G - (Delta/R^sigma) G[:,i] (e_i - G[i,:])  (Sherman-Morrison).
+// Sites are taken in blocks B of K consecutive sites.  Within a block only G[B,B] is needed to
+// decide, so one wavefront runs the block sequentially on a K x K copy (no workgroup barrier),
+// recording for the m-th accepted flip at site j_m
+//     x_m = -(Delta/R) G_{m-1}[:, j_m],   y_m = e_{j_m} - G_{m-1}[j_m, :]   (block entries),
+// so that after the block G = G0 + X Y with the full columns/rows obtained row by row from
+//     X[r,m] = -(Delta_m/R_m) (G0[r, j_m] + sum_{m'<m} X[r,m'] Y[m', j_m])
+//     Y[m,c] = delta_{c,j_m} - G0[j_m, c] - sum_{m'<m} X[j_m, m'] Y[m', c]
+// and the rank-m correction applied as one MFMA product.
+template <typename WT>
+__device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np, K = c.K, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K2 = K * K;
+  int8_t* fl = c.f + (size_t)(l - 1) * np;
+  const uint64_t seed = c.st->seed;
+  const int64_t sweep = c.st->sweeps_done;
+  int64_t acc_total = 0;
+  for (int i0 = 0; i0 < n; i0 += K) {
+    const int kb = min(K, n - i0);
+    if (wave == 0) {
+      // ---- phase 1: one wavefront decides the block
+      for (int e = lane; e < kb * kb; e += 64) {
+        int r = e / kb, cc = e - r * kb;
+        c.gb[r * K + cc] = (double)c.G[0][(i0 + r) * np + i0 + cc];
+        c.gb[K2 + r * K + cc] = (double)c.G[1][(i0 + r) * np + i0 + cc];
+      }
+      if (lane < kb) {
+        c.ublk[lane] = accept_uniform(seed, sweep, l - 1, i0 + lane);
+        c.sblk[lane] = fl[i0 + lane];
+      }
+      wave_sync();
+      int m = 0;
+      double ldu = 0.0, ldd = 0.0;
+      int flg = 0;
+      int64_t ties = 0;
+      for (int ii = 0; ii < kb; ++ii) {
+        const int s = c.sblk[ii];
+        const double u = c.ublk[ii];
+        const double gu = c.gb[ii * K + ii], gd = c.gb[K2 + ii * K + ii];
+        const double du = a.dup[s > 0], dd = a.ddn[s > 0];
+        const double ru = 1.0 + du * (1.0 - gu), rd = 1.0 + dd * (1.0 - gd);
+        const double R = ru * rd;
+        bool ok = true;
+        if (!(fabs(R) < 1e300)) { flg |= FLAG_NONFINITE; ok = false; }
+        else if (R < 0.0) { flg |= FLAG_NEGATIVE; ok = false; }
+        if (ok && fabs(u - R) < 1e-9) ++ties;
+        if (ok && u < R) {
+          const double cu = du / ru, cd = dd / rd;
+          // records x_m (column) and y_m (row) on the block, both spins
+          if (lane < kb) {
+            const int r = lane;
+            c.xb[r * K + m] = -cu * c.gb[r * K + ii];
+            c.xb[K2 + r * K + m] = -cd * c.gb[K2 + r * K + ii];
+            c.yb[m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[ii * K + r];
+            c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
+          }
+          wave_sync();
+          for (int e = lane; e < kb * kb; e += 64) {
+            int r = e / kb, cc = e - r * kb;
+            c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
+            c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
+          }
+          if (lane == 0) {
+            c.site[m] = ii;
+            c.cfu[m] = cu;
+            c.cfd[m] = cd;
+            fl[i0 + ii] = (int8_t)(-s);
+          }
+          ldu += log(fabs(ru));
+          ldd += log(fabs(rd));
+          ++m;
+          wave_sync();
+        }
+      }
+      if (lane == 0) {
+        c.cnt[0] = m;
+        ldrun[0] += ldu;
+        ldrun[1] += ldd;
+        if (flg) atomicOr(&c.st->flags, flg);
+        c.st->near_ties += ties;
+      }
+    }
+    __syncthreads();
+    const int m = c.cnt[0];
+    acc_total += m;
+    if (m == 0) continue;
+    const int mp = (m + 3) & ~3;
+    // ---- phase 2: full panels X (np x mp, column-major) and Y (mp x np, row-major), both spins
+    {
+      WT* X0 = c.xy;
+      WT* Y0 = c.xy + (size_t)np * K;
+      WT* X1 = c.xy + 2 * (size_t)np * K;
+      WT* Y1 = c.xy + 3 * (size_t)np * K;
+      for (int e = tid; e < 4 * np; e += NT) {
+        const int kind = e / (2 * np);          // 0: X rows, 1: Y columns
+        const int sp = (e / np) & 1;
+        const int r = e - (e / np) * np;        // row (X) or column (Y)
+        const WT* G0 = c.G[sp];
+        const double* cf = sp ? c.cfd : c.cfu;
+        const double* xbs = c.xb + sp * K2;
+        const double* ybs = c.yb + sp * K2;
+        double tmp[64];
+        if (kind == 0) {
+          WT* X = sp ? X1 : X0;
+          for (int t = 0; t < m; ++t) {
+            const int jt = c.site[t];
+            double acc = (r < n) ? (double)G0[r * np + i0 + jt] : 0.0;
+            for (int t2 = 0; t2 < t; ++t2) acc += tmp[t2] * ybs[t2 * K + jt];
+            tmp[t] = -cf[t] * acc;
+            X[t * np + r] = (WT)tmp[t];
+          }
+          for (int t = m; t < mp; ++t) X[t * np + r] = (WT)0;
+        } else {
+          WT* Y = sp ? Y1 : Y0;
+          for (int t = 0; t < m; ++t) {
+            const int jt = c.site[t];
+            double acc = ((r == i0 + jt) ? 1.0 : 0.0) - ((r < n) ? (double)G0[(i0 + jt) * np + r] : 0.0);
+            for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * K + t2] * tmp[t2];
+            if (r >= n) acc = 0.0;
+            tmp[t] = acc;
+            Y[t * np + r] = (WT)acc;
+          }
+          for (int t = m; t < mp; ++t) Y[t * np + r] = (WT)0;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- phase 3: G += X Y (rank mp) for both spins
+    {
+      WT* X0 = c.xy;
+      WT* Y0 = c.xy + (size_t)np * K;
+      WT* X1 = c.xy + 2 * (size_t)np * K;
+      WT* Y1 = c.xy + 3 * (size_t)np * K;
+      wg_gemm<WT>(2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1,
+                  [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    c.st->attempted += n;
+    c.st->accepted += acc_total;
+  }
+}
+
+// ------------------------------------------------------------------------------ stacks
+// Pointers into the right stack (entry j: UDT of B(L, j*stab)^T) and the left factors.
+template <typename WT>
+__device__ __forceinline__ double* stkU(Ctx<WT>& c, int sp, int j) {
+  const size_t nn = (size_t)c.np * c.np;
+  return c.stack + ((size_t)sp * c.J + j) * (2 * nn + c.np);
+}
+template <typename WT>
+__device__ __forceinline__ double* stkT(Ctx<WT>& c, int sp, int j) { return stkU(c, sp, j) + (size_t)c.np * c.np; }
+template <typename WT>
+__device__ __forceinline__ double* stkD(Ctx<WT>& c, int sp, int j) { return stkU(c, sp, j) + 2 * (size_t)c.np * c.np; }
+template <typename WT>
+__device__ __forceinline__ double* lftU(Ctx<WT>& c, int sp) {
+  const size_t nn = (size_t)c.np * c.np;
+  return c.left + (size_t)sp * (3 * nn + c.np);
+}
+template <typename WT>
+__device__ __forceinline__ double* lftT(Ctx<WT>& c, int sp, int k) { return lftU(c, sp) + (size_t)(1 + k) * c.np * c.np; }
+template <typename WT>
+__device__ __forceinline__ double* lftD(Ctx<WT>& c, int sp) { return lftU(c, sp) + 3 * (size_t)c.np * c.np; }
+
+// Build stack entries j = J-1 down to j_lo: entry j = UDT of B(L, j*stab)^T.
+template <typename WT>
+__device__ void build_right(Ctx<WT>& c, int j_lo) {
+  const KArgs& a = *c.a;
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int j = c.J - 1; j >= j_lo; --j) {
+      const int lo = j * c.stab, hi = min(c.L, (j + 1) * c.stab);
+      const bool top = (j == c.J - 1);
+      udt_push(c, sp, true, lo, hi, top ? a.eye : stkU(c, sp, j + 1), top ? a.ones : stkD(c, sp, j + 1),
+               top ? a.eye : stkT(c, sp, j + 1), stkU(c, sp, j), stkD(c, sp, j), stkT(c, sp, j));
+    }
+  }
+}
+
+// Load the working G from the FP64 record.
+template <typename WT>
+__device__ void load_green(Ctx<WT>& c) {
+  const size_t nn = (size_t)c.np * c.np;
+  for (size_t e = threadIdx.x; e < 2 * nn; e += NT) {
+    int sp = (int)(e / nn);
+    c.G[sp][e - sp * nn] = (WT)c.G64[e];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------ operations
+template <typename WT>
+__device__ void op_init(Ctx<WT>& c, int chain) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np, L = c.L, tid = threadIdx.x;
+  // fields: drawn from the seed or copied and validated
+  const uint64_t seed = c.st->seed;
+  for (int e = tid; e < L * np; e += NT) {
+    int l = e / np, i = e - l * np;
+    int8_t v = 0;
+    if (i < n) {
+      if (a.gen_fields) {
+        const int ee = l * n + i;
+        u64x4 w = philox4x64_10(u64x4{(uint64_t)(ee >> 2), 0ull, 0ull, 0ull}, seed, 0ull);
+        uint64_t word = (ee & 3) == 0 ? w.x0 : (ee & 3) == 1 ? w.x1 : (ee & 3) == 2 ? w.x2 : w.x3;
+        v = (word & 1ull) ? 1 : -1;
+      } else {
+        v = a.fields_in[((size_t)chain * L + l) * n + i];
+        if (v != 1 && v != -1) { atomicOr(a.err, 1); v = 1; }
+      }
+    }
+    c.f[e] = v;
+  }
+  __syncthreads();
+  build_right(c, 0);
+  double ld;
+  for (int sp = 0; sp < 2; ++sp) {
+    fresh_green(c, sp, a.eye, a.ones, a.eye, stkU(c, sp, 0), stkD(c, sp, 0), stkT(c, sp, 0),
+                c.G64 + (size_t)sp * np * np, &ld, false);
+    if (tid == 0) c.st->logdet[sp] = ld;
+  }
+  __syncthreads();
+}
+
+template <typename WT>
+__device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
+  const KArgs& a = *c.a;
+  const int np = c.np, L = c.L, tid = threadIdx.x;
+  load_green(c);
+  for (int s = 0; s < n_sweeps; ++s) {
+    build_right(c, 1);
+    double* ldrun = c.misc;   // running log|det| per spin from accepted ratios
+    if (tid == 0) { ldrun[0] = c.st->logdet[0]; ldrun[1] = c.st->logdet[1]; }
+    __syncthreads();
+    int cur = 0;     // which left T buffer is current
+    int l_prev = 0;  // last stabilisation slice
+    for (int l = 1; l <= L; ++l) {
+      wrap_both(c, l);
+      metropolis_slice(c, l, ldrun);
+      __syncthreads();
+      if (l % c.stab == 0 || l == L) {
+        const int jr = l / c.stab;   // stack entry at l (unused when l == L)
+        for (int sp = 0; sp < 2; ++sp) {
+          const bool first = (l_prev == 0);
+          udt_push(c, sp, false, l_prev, l, first ? a.eye : lftU(c, sp), first ? a.ones : lftD(c, sp),
+                   first ? a.eye : lftT(c, sp, cur), lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1));
+          double ld;
+          const bool last = (l == L);
+          double dr = fresh_green(c, sp, lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1),
+                                  last ? a.eye : stkU(c, sp, jr), last ? a.ones : stkD(c, sp, jr),
+                                  last ? a.eye : stkT(c, sp, jr),
+                                  last ? c.G64 + (size_t)sp * np * np : nullptr, &ld, true);
+          if (tid == 0) {
+            ChainStats* st = c.st;
+            if (dr > st->max_drift || dr != dr) st->max_drift = dr;
+            if (!(dr <= a.drift_limit)) st->flags |= FLAG_DRIFT;
+            double e = fabs(ld - ldrun[sp]);
+            if (e > st->max_logdet_err) st->max_logdet_err = e;
+            ldrun[sp] = ld;
+          }
+          __syncthreads();
+        }
+        cur ^= 1;
+        l_prev = l;
+      }
+    }
+    if (tid == 0) {
+      c.st->logdet[0] = ldrun[0];
+      c.st->logdet[1] = ldrun[1];
+      c.st->sweeps_done += 1;
+    }
+    __syncthreads();
+  }
+}
+
+// Fresh G(slice) of the current field from scratch (left chain from slice 1, right chain from
+// slice L, both chunked by stab), into the working G of both spins.
+template <typename WT>
+__device__ void fresh_at(Ctx<WT>& c, int slice) {
+  const KArgs& a = *c.a;
+  const int L = c.L;
+  for (int sp = 0; sp < 2; ++sp) {
+    // left: B(slice, 0) into the left buffers (T ping-pong)
+    int cur = 0;
+    bool have = false;
+    for (int lo = 0; lo < slice; lo += c.stab) {
+      const int hi = min(slice, lo + c.stab);
+      udt_push(c, sp, false, lo, hi, have ? lftU(c, sp) : a.eye, have ? lftD(c, sp) : a.ones,
+               have ? lftT(c, sp, cur) : a.eye, lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1));
+      cur ^= 1;
+      have = true;
+    }
+    // right: B(L, slice)^T into stack slot 0 (T ping-pong through slot 1's T when J > 1)
+    bool rhave = false;
+    int rcur = 0;
+    double* rT[2] = {stkT(c, sp, 0), c.J > 1 ? stkT(c, sp, 1) : stkT(c, sp, 0)};
+    for (int hi = L; hi > slice; hi -= c.stab) {
+      const int lo = max(slice, hi - c.stab);
+      udt_push(c, sp, true, lo, hi, rhave ? stkU(c, sp, 0) : a.eye, rhave ? stkD(c, sp, 0) : a.ones,
+               rhave ? rT[rcur] : a.eye, stkU(c, sp, 0), stkD(c, sp, 0), rT[rcur ^ 1]);
+      rcur ^= 1;
+      rhave = true;
+    }
+    double ld;
+    fresh_green(c, sp, have ? lftU(c, sp) : a.eye, have ? lftD(c, sp) : a.ones,
+                have ? lftT(c, sp, cur) : a.eye, rhave ? stkU(c, sp, 0) : a.eye,
+                rhave ? stkD(c, sp, 0) : a.ones, rhave ? rT[rcur] : a.eye, nullptr, &ld, false);
+  }
+}
+
+template <typename WT>
+__device__ void op_debug_green(Ctx<WT>& c, int chain) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np;
+  fresh_at(c, a.slice);
+  for (int w = 1; w <= a.n_wraps; ++w) wrap_both(c, a.slice + w);
+  double* out = a.out + (size_t)chain * 2 * n * n;
+  for (int e = threadIdx.x; e < 2 * n * n; e += NT) {
+    int sp = e / (n * n), r = (e / n) % n, col = e % n;
+    out[e] = (double)c.G[sp][r * np + col];
+  }
+}
+
+template <typename WT>
+__device__ void op_debug_ratios(Ctx<WT>& c, int chain) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np;
+  fresh_at(c, a.slice);
+  const int8_t* fl = c.f + (size_t)(a.slice - 1) * np;
+  double* out = a.out + (size_t)chain * 2 * n;
+  for (int e = threadIdx.x; e < 2 * n; e += NT) {
+    int sp = e / n, i = e % n;
+    int s = fl[i];
+    double d = sp ? a.ddn[s > 0] : a.dup[s > 0];
+    out[e] = 1.0 + d * (1.0 - (double)c.G[sp][i * np + i]);
+  }
+}
+
+}  // namespace dqmc

@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libdqmc.so (include/dqmc.h).
+
+Argument marshalling only: PyTorch supplies device memory (the workspace, fields and output
+buffers are torch tensors on the GPU) and streams; every step of the sweep runs in the HIP
+kernels of the library.  There is no CPU fallback: without the built library, or without a GPU,
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdqmc.so")
+
+FP64 = 0
+FP32_WRAP = 1
+PRECISIONS = {"fp64": FP64, "fp32_wrap": FP32_WRAP}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EBUSY"}
+FLAG_NONFINITE, FLAG_NEGATIVE, FLAG_DRIFT, FLAG_SINGULAR = 1, 2, 4, 8
+
+
+class DqmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dqmc {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("hopping", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_double), ("mu", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32), ("delay_rank", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+OBS_DTYPE = np.dtype([("double_occ", "f8"), ("density", "f8"), ("kinetic", "f8"),
+                      ("logdet_up", "f8"), ("logdet_dn", "f8"), ("max_drift", "f8"),
+                      ("max_logdet_err", "f8"), ("attempted", "i8"), ("accepted", "i8"),
+                      ("near_ties", "i8"), ("sweeps_done", "i8"), ("flags", "i4"),
+                      ("reserved", "i4")])
+
+_lib = None
+_vp, _i32, _u64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+
+_SIGS = {
+    "dqmc_chain_bytes": (_sz, [ctypes.POINTER(Model)]),
+    "dqmc_workspace_bytes": (_sz, [ctypes.POINTER(Model), _i32]),
+    "dqmc_init_chains": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(Model), _i32, _vp,
+                                ctypes.POINTER(_u64), _vp, _sz, _vp]),
+    "dqmc_sweep": (_i32, [_vp, _i32, _vp]),
+    "dqmc_sweep_multi": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32, _vp]),
+    "dqmc_measure": (_i32, [_vp, _vp, _vp, _vp]),
+    "dqmc_get_fields": (_i32, [_vp, _vp, _vp]),
+    "dqmc_destroy": (_i32, [_vp]),
+    "dqmc_last_error": (ctypes.c_char_p, []),
+    "dqmc_batch_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                               ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "dqmc_debug_green": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "dqmc_debug_ratios": (_i32, [_vp, _i32, _vp, _vp]),
+    "dqmc_debug_propagators": (_i32, [_vp, _vp, _vp]),
+    "dqmc_debug_philox": (_i32, [_u64, _u64, _u64, _u64, _u64, _u64, _i32, _vp, _vp]),
+    "dqmc_debug_mfma": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+}
+
+
+def lib():
+    """Load libdqmc.so (built in-tree by build.build()); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise DqmcError(status, lib().dqmc_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libdqmc needs a ROCm GPU; torch.cuda.is_available() is False")
+    return torch
+
+
+def _stream(stream, device):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, delay_rank=0,
+               precision="fp64"):
+    """Build the C model struct; the returned object keeps the host hopping array alive."""
+    T = np.ascontiguousarray(np.asarray(hopping, dtype=np.float64))
+    if T.ndim != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("hopping must be N x N")
+    m = Model()
+    m.n_sites = T.shape[0]
+    m.hopping = T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    m.U, m.mu, m.dtau = float(U), float(mu), float(dtau)
+    m.n_slices, m.stab_every = int(n_slices), int(stab_every)
+    m.refresh_every, m.delay_rank = int(refresh_every), int(delay_rank)
+    m.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    m._keep = T
+    return m
+
+
+def chain_bytes(model: Model) -> int:
+    return int(lib().dqmc_chain_bytes(ctypes.byref(model)))
+
+
+def workspace_bytes(model: Model, n_chains: int) -> int:
+    return int(lib().dqmc_workspace_bytes(ctypes.byref(model), int(n_chains)))
+
+
+class Batch:
+    """A batch of independent DQMC chains of one model, resident on one GPU."""
+
+    def __init__(self, model: Model, seeds, fields=None, device="cuda:0", stream=None,
+                 workspace=None):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.model = model
+        self.n = model.n_sites
+        self.L = model.n_slices
+        seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        self.n_chains = int(seeds.shape[0])
+        self.seeds = seeds
+        nbytes = workspace_bytes(model, self.n_chains)
+        if nbytes == 0:
+            _check(-1)
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws = workspace
+        base = workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self._ws_bytes = workspace.numel() - (self._ws_ptr - base)
+        if fields is not None:
+            if isinstance(fields, torch.Tensor):
+                f = fields
+            else:
+                f = torch.as_tensor(np.ascontiguousarray(np.asarray(fields, dtype=np.int8)))
+            f = f.to(device=self.device, dtype=torch.int8).contiguous()
+            if tuple(f.shape) != (self.n_chains, self.L, self.n):
+                raise ValueError(f"fields must be [{self.n_chains}][{self.L}][{self.n}]")
+            self._fields_in = f
+            fptr = _ptr(f)
+        else:
+            self._fields_in = None
+            fptr = ctypes.c_void_p(0)
+        h = ctypes.c_void_p()
+        s = _stream(stream, self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_init_chains(ctypes.byref(h), ctypes.byref(model), self.n_chains, fptr,
+                                          seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          ctypes.c_void_p(self._ws_ptr), self._ws_bytes, s))
+        self._h = h
+        self._fields_in = None
+        k, st, ldsb, var = _i32(), _i32(), _i32(), _i32()
+        _check(lib().dqmc_batch_info(h, ctypes.byref(k), ctypes.byref(st), ctypes.byref(ldsb),
+                                     ctypes.byref(var)))
+        self.delay_rank, self.stab, self.lds_bytes, self.variant = k.value, st.value, ldsb.value, var.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sweep(self, n_sweeps: int, stream=None):
+        with self.torch.cuda.device(self.device):
+            _check(lib().dqmc_sweep(self._h, int(n_sweeps), _stream(stream, self.device)))
+
+    def measure(self, green: bool = False, stream=None):
+        """Per-chain observables (numpy structured array) and optionally G(0) [c][2][N][N]."""
+        torch = self.torch
+        obs = torch.empty(self.n_chains * OBS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        g = torch.empty((self.n_chains, 2, self.n, self.n), dtype=torch.float64,
+                        device=self.device) if green else None
+        with torch.cuda.device(self.device):
+            st = lib().dqmc_measure(self._h, _ptr(obs), _ptr(g) if g is not None else None,
+                                    _stream(stream, self.device))
+        if st not in (0, -4):
+            _check(st)
+        o = np.frombuffer(obs.cpu().numpy().tobytes(), dtype=OBS_DTYPE)
+        return (o, g) if green else o
+
+    def fields(self, stream=None):
+        torch = self.torch
+        out = torch.empty((self.n_chains, self.L, self.n), dtype=torch.int8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_get_fields(self._h, _ptr(out), _stream(stream, self.device)))
+        return out
+
+    def debug_green(self, slice_: int, n_wraps: int = 0, stream=None):
+        torch = self.torch
+        out = torch.empty((self.n_chains, 2, self.n, self.n), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_debug_green(self._h, int(slice_), int(n_wraps), _ptr(out),
+                                          _stream(stream, self.device)))
+        return out
+
+    def debug_ratios(self, slice_: int, stream=None):
+        torch = self.torch
+        out = torch.empty((self.n_chains, 2, self.n), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_debug_ratios(self._h, int(slice_), _ptr(out), _stream(stream, self.device)))
+        return out
+
+    def propagators(self, stream=None):
+        torch = self.torch
+        out = torch.empty((2, self.n, self.n), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_debug_propagators(self._h, _ptr(out), _stream(stream, self.device)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dqmc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sweep_multi(batches, n_sweeps, stream=None):
+    """Sweep several batches together (one launch each, overlapping on forked streams)."""
+    if not batches:
+        return
+    torch = batches[0].torch
+    hs = (ctypes.c_void_p * len(batches))(*[b.handle.value for b in batches])
+    ns = (ctypes.c_int32 * len(batches))(*[int(x) for x in n_sweeps])
+    dev = batches[0].device
+    with torch.cuda.device(dev):
+        _check(lib().dqmc_sweep_multi(hs, ns, len(batches), _stream(stream, dev)))
+
+
+def debug_philox(key, ctr, n_blocks, device="cuda:0"):
+    torch = _torch()
+    out = torch.empty((n_blocks, 4), dtype=torch.uint64, device=device)
+    with torch.cuda.device(device):
+        _check(lib().dqmc_debug_philox(key[0], key[1], ctr[0], ctr[1], ctr[2], ctr[3], n_blocks,
+                                       _ptr(out), _stream(None, torch.device(device))))
+    return out
+
+
+def debug_mfma(a64, b64, a32, b32, device="cuda:0"):
+    torch = _torch()
+    dev = torch.device(device)
+    ta64 = torch.as_tensor(a64, dtype=torch.float64, device=dev).contiguous()
+    tb64 = torch.as_tensor(b64, dtype=torch.float64, device=dev).contiguous()
+    ta32 = torch.as_tensor(a32, dtype=torch.float32, device=dev).contiguous()
+    tb32 = torch.as_tensor(b32, dtype=torch.float32, device=dev).contiguous()
+    o64 = torch.zeros((16, 16), dtype=torch.float64, device=dev)
+    o32 = torch.zeros((16, 16), dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib().dqmc_debug_mfma(_ptr(ta64), _ptr(tb64), _ptr(o64), _ptr(ta32), _ptr(tb32),
+                                     _ptr(o32), _stream(None, dev)))
+    return o64, o32
