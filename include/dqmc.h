@@ -129,7 +129,8 @@ dqmc_status dqmc_destroy(dqmc_batch* b);
 const char* dqmc_last_error(void);
 
 /* Numbers the library chose: site-block size k, stabilisation interval, LDS bytes of the sweep
- * kernel, and the kernel variant (0 = LDS-resident Green's function, 1 = global-memory). */
+ * kernel, and the sweep kernel variant (0 = generic with LDS-resident Green's functions,
+ * 1 = generic with Green's functions in the workspace, 2 = the N <= 64 register/LDS path). */
 dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int32_t* lds_bytes,
                             int32_t* variant);
 
@@ -148,6 +149,14 @@ dqmc_status dqmc_debug_ratios(dqmc_batch* b, int32_t slice, double* out, void* s
 /* The propagators e^{-dtau (T - mu)} and e^{+dtau (T - mu)} the batch computed on the device.
  * out: DEVICE double [2][N][N]. */
 dqmc_status dqmc_debug_propagators(dqmc_batch* b, double* out, void* stream);
+
+/* Wall-clock ticks (100 MHz) each chain's workgroup spent per phase of its sweeps since init:
+ * [0] right stack, [1] wraps, [2] Metropolis decisions, [3] delayed-update panels, [4] rank-m
+ * flushes, [5] left UDT, [6] fresh G, [7] whole sweeps; finer split of the stabilisation work
+ * (N <= 64 path): [8] B-chunk products, [9] QR factorisation, [10] forming Q, [11] T products,
+ * [12] fresh-G products, [13] Gauss-Jordan, [14] fresh-G output product, [15] parking G.
+ * out: DEVICE int64 [n_chains][16]. */
+dqmc_status dqmc_debug_phase_ticks(dqmc_batch* b, int64_t* out, void* stream);
 
 /* Raw Philox4x64-10 blocks of the device generator: for counters (c0 + j, c1, c2, c3),
  * j = 0 .. n_blocks-1, key (k0, k1), the four words into out (DEVICE uint64 [n_blocks][4]). */

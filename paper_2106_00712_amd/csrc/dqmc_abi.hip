@@ -12,6 +12,7 @@
 
 #include "dqmc.h"
 #include "dqmc_device.hpp"
+#include "dqmc_fast.hpp"
 
 using namespace dqmc;
 
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
       st->logdet[0] = st->logdet[1] = 0.0;
       st->flags = 0;
       st->pad = 0;
+      for (int k = 0; k < 16; ++k) st->ticks[k] = 0;
     }
     __syncthreads();
     op_init(c, chain);
@@ -115,6 +117,14 @@ __global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
   } else if (a.op == OP_DEBUG_RATIOS) {
     op_debug_ratios(c, chain);
   }
+}
+
+template <int NP, typename WT, int KB>
+__global__ __launch_bounds__(NT) void fast_sweep_kernel(KArgs a) {
+  extern __shared__ double lds[];
+  const int chain = blockIdx.x;
+  if (chain >= a.n_chains) return;
+  fast::Fast<NP, WT, KB>::run(a, chain, lds);
 }
 
 // ------------------------------------------------------------------------ measurements
@@ -194,6 +204,13 @@ __global__ void copy_propagators_kernel(KArgs a) {
   }
 }
 
+__global__ void phase_ticks_kernel(KArgs a, int64_t* out) {
+  int chain = blockIdx.x * blockDim.x + threadIdx.x;
+  if (chain >= a.n_chains) return;
+  const ChainStats* st = (const ChainStats*)(a.base + (size_t)chain * a.stride + a.o_stats);
+  for (int k = 0; k < 16; ++k) out[(size_t)chain * 16 + k] = st->ticks[k];
+}
+
 __global__ void philox_kernel(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
                               uint64_t c3, int n_blocks, uint64_t* out) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -225,8 +242,8 @@ __global__ void mfma_probe_kernel(const double* a64, const double* b64, double* 
 // ------------------------------------------------------------------------ the handle
 struct dqmc_batch {
   int n, np, L, stab, J, K, n_chains, precision;
-  bool small;
-  size_t lds_bytes;
+  bool small, fast;
+  size_t lds_bytes, fast_lds_bytes;
   KArgs args;   // base arguments (op fields filled per call)
   char* ws;
   size_t ws_bytes;
@@ -236,8 +253,8 @@ namespace {
 
 struct Layout {
   int n, np, L, stab, J, K, precision;
-  bool small;
-  size_t lds_bytes;
+  bool small, fast;
+  size_t lds_bytes, fast_lds_bytes;
   // constants region (offsets from the workspace base)
   size_t c_expK, c_expKinv, c_expK32, c_expKinv32, c_T, c_eye, c_ones, c_A, c_E0, c_E1, c_seeds,
       c_err, c_end;
@@ -300,6 +317,26 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
     L.lds_bytes = lds_vec_doubles(L.np, L.K) * sizeof(double);
     if (L.lds_bytes > (size_t)lds_limit) return fail(DQMC_EINVAL, "n_sites too large for LDS vectors");
   }
+  // fast sweep path: padded size 16, 32 or 64, block size 8 or 16 sites
+  L.fast = false;
+  L.fast_lds_bytes = 0;
+  if (L.np == 16 || L.np == 32 || L.np == 64) {
+    const int kb = (kreq <= 8 || L.np == 16) ? 8 : 16;
+    size_t fb = 0;
+    const bool f32 = wts == 4;
+#define DQMC_FB(NPV, KBV) (f32 ? fast::Fast<NPV, float, KBV>::lds_bytes() : fast::Fast<NPV, double, KBV>::lds_bytes())
+    if (L.np == 16) fb = DQMC_FB(16, 8);
+    else if (L.np == 32) fb = kb == 8 ? DQMC_FB(32, 8) : DQMC_FB(32, 16);
+    else fb = kb == 8 ? DQMC_FB(64, 8) : DQMC_FB(64, 16);
+#undef DQMC_FB
+    if (fb <= (size_t)lds_limit) {
+      L.fast = true;
+      L.fast_lds_bytes = fb;
+      L.K = kb;   // one block size for both kernels, so that init/debug and sweeps agree
+      if (L.small) L.lds_bytes = small_bytes(L.K);
+      if (L.lds_bytes > (size_t)lds_limit) return fail(DQMC_EINVAL, "LDS budget exceeded");
+    }
+  }
   // constants
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
@@ -324,12 +361,12 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   L.o_G64 = ctake(2 * nn * 8);
   L.o_stack = ctake(2 * (size_t)L.J * (2 * nn + L.np) * 8);
   L.o_left = ctake(2 * (3 * nn + L.np) * 8);
+  L.o_Gw = ctake(2 * nn * 8);   // working G of the global variant / parked G of the fast path
   if (!L.small) {
-    L.o_Gw = ctake(2 * nn * wts);
     L.o_work = ctake(2 * nn * 8);
     L.o_xy = ctake(4 * (size_t)L.np * L.K * wts);
   } else {
-    L.o_Gw = L.o_work = L.o_xy = 0;
+    L.o_work = L.o_xy = 0;
   }
   L.stride = align256(co);
   *out = L;
@@ -374,9 +411,28 @@ dqmc_status launch_chain(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
   return DQMC_OK;
 }
 
+template <int NP, typename WT, int KB>
+dqmc_status launch_fast_t(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
+  auto kern = fast_sweep_kernel<NP, WT, KB>;
+  const size_t bytes = fast::Fast<NP, WT, KB>::lds_bytes();
+  if (bytes > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(kern, dim3(b->n_chains), dim3(NT), bytes, s, a);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+template <typename WT>
+dqmc_status launch_fast(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
+  if (b->np == 16) return launch_fast_t<16, WT, 8>(b, a, s);
+  if (b->np == 32) return b->K == 8 ? launch_fast_t<32, WT, 8>(b, a, s) : launch_fast_t<32, WT, 16>(b, a, s);
+  return b->K == 8 ? launch_fast_t<64, WT, 8>(b, a, s) : launch_fast_t<64, WT, 16>(b, a, s);
+}
+
 dqmc_status launch(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
   if (b->n_chains == 0) return DQMC_OK;
   const bool f32 = b->precision == DQMC_FP32_WRAP;
+  if (a.op == OP_SWEEP && b->fast) return f32 ? launch_fast<float>(b, a, s) : launch_fast<double>(b, a, s);
   if (f32) return b->small ? launch_chain<float, true>(b, a, s) : launch_chain<float, false>(b, a, s);
   return b->small ? launch_chain<double, true>(b, a, s) : launch_chain<double, false>(b, a, s);
 }
@@ -447,6 +503,7 @@ dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_ch
   if (!b) return fail(DQMC_EDEVICE, "host allocation failed");
   b->n = L.n; b->np = L.np; b->L = L.L; b->stab = L.stab; b->J = L.J; b->K = L.K;
   b->n_chains = n_chains; b->precision = L.precision; b->small = L.small; b->lds_bytes = L.lds_bytes;
+  b->fast = L.fast; b->fast_lds_bytes = L.fast_lds_bytes;
   b->ws = ws; b->ws_bytes = ws_bytes;
   fill_args(L, m, ws, n_chains, &b->args);
   KArgs a = b->args;
@@ -553,8 +610,8 @@ dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int3
   if (!b) return fail(DQMC_EINVAL, "batch is NULL");
   if (k) *k = b->K;
   if (stab) *stab = b->stab;
-  if (lds_bytes) *lds_bytes = (int32_t)b->lds_bytes;
-  if (variant) *variant = b->small ? 0 : 1;
+  if (lds_bytes) *lds_bytes = (int32_t)(b->fast ? b->fast_lds_bytes : b->lds_bytes);
+  if (variant) *variant = b->fast ? 2 : (b->small ? 0 : 1);
   return DQMC_OK;
 }
 
@@ -584,6 +641,15 @@ dqmc_status dqmc_debug_propagators(dqmc_batch* b, double* out, void* stream) {
   KArgs a = b->args;
   a.out = out;
   hipLaunchKernelGGL(copy_propagators_kernel, dim3(16), dim3(256), 0, (hipStream_t)stream, a);
+  HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_debug_phase_ticks(dqmc_batch* b, int64_t* out, void* stream) {
+  if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
+  if (b->n_chains == 0) return DQMC_OK;
+  hipLaunchKernelGGL(phase_ticks_kernel, dim3((b->n_chains + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, b->args, out);
   HIP_TRY(hipGetLastError());
   return DQMC_OK;
 }

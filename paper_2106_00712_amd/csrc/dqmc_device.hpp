@@ -31,6 +31,21 @@ struct ChainStats {
   double max_drift, max_logdet_err;
   double logdet[2];
   int32_t flags, pad;
+  int64_t ticks[16];  // wall-clock ticks (100 MHz) spent per phase, see enum Phase
+};
+
+// Phases of a sweep timed by thread 0 between workgroup barriers.
+enum Phase { PH_RIGHT = 0, PH_WRAP = 1, PH_DECIDE = 2, PH_PANEL = 3, PH_FLUSH = 4, PH_LEFT = 5,
+             PH_FRESH = 6, PH_SWEEP = 7,
+             // finer split of the stabilisation work (fast path)
+             PH_CHUNK = 8, PH_QR = 9, PH_QFORM = 10, PH_TMUL = 11, PH_FGEMM = 12, PH_GJ = 13,
+             PH_GOUT = 14, PH_PARK = 15 };
+struct PhaseClock {
+  int64_t t;
+  __device__ __forceinline__ void start() { if (threadIdx.x == 0) t = wall_clock64(); }
+  __device__ __forceinline__ void stop(ChainStats* st, int ph) {
+    if (threadIdx.x == 0) { int64_t e = wall_clock64(); st->ticks[ph] += e - t; t = e; }
+  }
 };
 
 // Everything a kernel launch needs (passed by value).
@@ -682,6 +697,8 @@ __device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
   const uint64_t seed = c.st->seed;
   const int64_t sweep = c.st->sweeps_done;
   int64_t acc_total = 0;
+  PhaseClock clk;
+  clk.start();
   for (int i0 = 0; i0 < n; i0 += K) {
     const int kb = min(K, n - i0);
     if (wave == 0) {
@@ -748,6 +765,7 @@ __device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
       }
     }
     __syncthreads();
+    clk.stop(c.st, PH_DECIDE);
     const int m = c.cnt[0];
     acc_total += m;
     if (m == 0) continue;
@@ -792,6 +810,7 @@ __device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
       }
     }
     __syncthreads();
+    clk.stop(c.st, PH_PANEL);
     // ---- phase 3: G += X Y (rank mp) for both spins
     {
       WT* X0 = c.xy;
@@ -802,6 +821,7 @@ __device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
                   [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
     }
     __syncthreads();
+    clk.stop(c.st, PH_FLUSH);
   }
   if (tid == 0) {
     c.st->attempted += n;
@@ -894,23 +914,31 @@ __device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
   const KArgs& a = *c.a;
   const int np = c.np, L = c.L, tid = threadIdx.x;
   load_green(c);
+  PhaseClock clk, total;
   for (int s = 0; s < n_sweeps; ++s) {
+    total.start();
+    clk.start();
     build_right(c, 1);
+    clk.stop(c.st, PH_RIGHT);
     double* ldrun = c.misc;   // running log|det| per spin from accepted ratios
     if (tid == 0) { ldrun[0] = c.st->logdet[0]; ldrun[1] = c.st->logdet[1]; }
     __syncthreads();
     int cur = 0;     // which left T buffer is current
     int l_prev = 0;  // last stabilisation slice
     for (int l = 1; l <= L; ++l) {
+      clk.start();
       wrap_both(c, l);
+      clk.stop(c.st, PH_WRAP);
       metropolis_slice(c, l, ldrun);
       __syncthreads();
+      clk.start();
       if (l % c.stab == 0 || l == L) {
         const int jr = l / c.stab;   // stack entry at l (unused when l == L)
         for (int sp = 0; sp < 2; ++sp) {
           const bool first = (l_prev == 0);
           udt_push(c, sp, false, l_prev, l, first ? a.eye : lftU(c, sp), first ? a.ones : lftD(c, sp),
                    first ? a.eye : lftT(c, sp, cur), lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1));
+          clk.stop(c.st, PH_LEFT);
           double ld;
           const bool last = (l == L);
           double dr = fresh_green(c, sp, lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1),
@@ -926,6 +954,7 @@ __device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
             ldrun[sp] = ld;
           }
           __syncthreads();
+          clk.stop(c.st, PH_FRESH);
         }
         cur ^= 1;
         l_prev = l;
@@ -937,6 +966,7 @@ __device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
       c.st->sweeps_done += 1;
     }
     __syncthreads();
+    total.stop(c.st, PH_SWEEP);
   }
 }
 

@@ -63,6 +63,7 @@ _SIGS = {
     "dqmc_debug_green": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "dqmc_debug_ratios": (_i32, [_vp, _i32, _vp, _vp]),
     "dqmc_debug_propagators": (_i32, [_vp, _vp, _vp]),
+    "dqmc_debug_phase_ticks": (_i32, [_vp, _vp, _vp]),
     "dqmc_debug_philox": (_i32, [_u64, _u64, _u64, _u64, _u64, _u64, _i32, _vp, _vp]),
     "dqmc_debug_mfma": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
@@ -229,6 +230,17 @@ class Batch:
         with torch.cuda.device(self.device):
             _check(lib().dqmc_debug_propagators(self._h, _ptr(out), _stream(stream, self.device)))
         return out
+
+    PHASES = ("right_stack", "wrap", "decide", "panel", "flush", "left_udt", "fresh_g", "sweep",
+              "chunk_gemm", "qr", "q_form", "t_gemm", "fresh_gemm", "gauss_jordan", "g_out", "park")
+
+    def phase_seconds(self, stream=None):
+        """Per-chain seconds spent in each phase of the sweeps so far ([n_chains][16])."""
+        torch = self.torch
+        out = torch.zeros((self.n_chains, 16), dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_debug_phase_ticks(self._h, _ptr(out), _stream(stream, self.device)))
+        return out.cpu().numpy() / 1.0e8
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
