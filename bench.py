@@ -30,8 +30,8 @@ PEAK_FP64_MFMA = 78.6e12     # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32_MFMA = 157.3e12    # MI355X dense FP32 matrix, FLOP/s
 WORKLOAD = "square8x8_U4_b4"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_00712_amd", "csrc", f)
-                  for f in ("dqmc_device.hpp", "dqmc_abi.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_kernel_square8x8.json")
+                  for f in ("dqmc_device.hpp", "dqmc_fast.hpp", "dqmc_stab.hpp", "dqmc_abi.hip")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast_sweep_kernel_square8x8.json")
 
 
 def algorithmic_flops(N: int, L: int, n_s: int, acc: float) -> dict:
@@ -137,12 +137,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=12)
     ap.add_argument("--cpu-sweeps", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: chains are independent, so a multi-GPU run is the "
               "one-GPU run per device; this build launches on one GPU only.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = di.WORKLOADS[WORKLOAD]
     upd_step = w.n_chains * w.n_slices * w.n_sites
     r64 = run_gpu(w, "fp64", args.steps, args.warmup, args.delay_rank, 0)
@@ -173,7 +182,8 @@ def main():
                    "lds_bytes": r64["batch"].lds_bytes},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": traffic,
-                     "kernel": "chain_kernel<double, LDS-resident> (OP_SWEEP)",
+                     "kernel": "fast_sweep_kernel<64, double, 16>" if r64["batch"].variant == 2
+                     else "chain_kernel<double> (OP_SWEEP)",
                      "launch_ms": t_launch * 1e3,
                      "flop_per_chain_sweep": fl, "acceptance": acc},
         "phase_share": r64["phase_share"],
