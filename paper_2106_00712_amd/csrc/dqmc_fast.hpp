@@ -246,9 +246,10 @@ struct Fast {
       DQMC_LDS double* sg = (DQMC_LDS double*)(L.sgn + sp * NP);
       DQMC_LDS int* rk = (DQMC_LDS int*)(L.rank + sp * NP);
       DQMC_LDS int* ov = (DQMC_LDS int*)(L.ordv + sp * NP);
-      stab::qr_factor<NP, 0>(n, X, vd, bt, rk, ov, dd, sg, &c.st->flags);
+      DQMC_LDS double* Vb = (DQMC_LDS double*)slot(L, nxt + sp);
+      stab::qr_factor<NP>(n, X, Vb, vd, bt, rk, ov, dd, sg, &c.st->flags);
       qc.stop(c.st, PH_QR);
-      stab::qr_form_q<NP>(n, X, vd, bt, ov, sg, Ud[sp]);
+      stab::qr_form_q<NP>(n, Vb, vd, bt, sg, Ud[sp]);
       qc.stop(c.st, PH_QFORM);
       // d to the workspace; T' = D^{-1} S R P^T in place (column c of R lives in lane c)
       const int cc = threadIdx.x & 63;
@@ -319,10 +320,11 @@ struct Fast {
     const int wave = tid >> 6;
     if (wave < 2) {
       const int sp = wave;
-      double la = stab::gj_inverse<NP, 0>(n, (const DQMC_LDS double*)slot(L, 2 + sp),
-                                          (DQMC_LDS double*)slot(L, sp),
-                                          (const DQMC_LDS double*)(iLb + sp * NP),
-                                          (DQMC_LDS int*)(L.ordv + sp * NP), &c.st->flags);
+      double la = stab::gj_inverse<NP>(n, (const DQMC_LDS double*)slot(L, 2 + sp),
+                                       (DQMC_LDS double*)slot(L, sp),
+                                       (const DQMC_LDS double*)(iLb + sp * NP),
+                                       (DQMC_LDS int*)(L.ordv + sp * NP),
+                                       (DQMC_LDS double*)(L.dd + sp * NP), &c.st->flags);
       if ((tid & 63) == 0) L.misc[8 + sp] = la;
     }
     __syncthreads();
@@ -488,34 +490,48 @@ struct Fast {
       WT* Y0 = X0 + NP * KB;
       WT* X1 = X0 + 2 * NP * KB;
       WT* Y1 = X0 + 3 * NP * KB;
-      // panels: X rows (threads 0 .. 2NP-1), Y columns (2NP .. 4NP-1)
+      // panels, one row of X or one column of Y per thread with the m terms in registers:
+      //   x_t = -c_t (G[:, a_t] + sum_{t'<t} x_t' y_t'[a_t]),  y_t = e_{a_t} - G[a_t, :] - sum_{t'<t} x_t'[a_t] y_t'
       for (int e = tid; e < 4 * NP; e += NT) {
         const int kind = e / (2 * NP), sp = (e / NP) & 1, r = e % NP;
         const WT* Gs = sp ? G1 : G0;
-        const double* cf = L.cf + sp * KB;
         const double* xbs = L.xb + sp * KB * KB;
         const double* ybs = L.yb + sp * KB * KB;
+        int at[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) at[t] = (t < m) ? L.site[t] : 0;
+        double v[KB];
         if (kind == 0) {
-          WT* X = sp ? X1 : X0;
-          for (int t = 0; t < m; ++t) {
-            const int jt = L.site[t];
-            double acc = (r < n) ? (double)Gs[r * NP + i0 + jt] : 0.0;
-            for (int t2 = 0; t2 < t; ++t2) acc += (double)X[t2 * NP + r] * ybs[t2 * KB + jt];
-            X[t * NP + r] = (WT)(-cf[t] * acc);
-          }
-          for (int t = m; t < mp; ++t) X[t * NP + r] = (WT)0;
-        } else {
-          WT* Y = sp ? Y1 : Y0;
-          for (int t = 0; t < m; ++t) {
-            const int jt = L.site[t];
-            double acc = 0.0;
-            if (r < n) {
-              acc = ((r == i0 + jt) ? 1.0 : 0.0) - (double)Gs[(i0 + jt) * NP + r];
-              for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * KB + t2] * (double)Y[t2 * NP + r];
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            v[t] = 0.0;
+            if (t < m) {
+              double acc = (double)Gs[r * NP + i0 + at[t]];
+#pragma unroll
+              for (int t2 = 0; t2 < t; ++t2) acc += v[t2] * ybs[t2 * KB + at[t]];
+              v[t] = -L.cf[sp * KB + t] * acc;
             }
-            Y[t * NP + r] = (WT)acc;
           }
-          for (int t = m; t < mp; ++t) Y[t * NP + r] = (WT)0;
+          WT* X = sp ? X1 : X0;
+#pragma unroll
+          for (int t = 0; t < KB; ++t)
+            if (t < mp) X[t * NP + r] = (WT)v[t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            v[t] = 0.0;
+            if (t < m) {
+              const int ia = i0 + at[t];
+              double acc = ((r == ia && r < n) ? 1.0 : 0.0) - (double)Gs[ia * NP + r];
+#pragma unroll
+              for (int t2 = 0; t2 < t; ++t2) acc -= xbs[at[t] * KB + t2] * v[t2];
+              v[t] = acc;
+            }
+          }
+          WT* Y = sp ? Y1 : Y0;
+#pragma unroll
+          for (int t = 0; t < KB; ++t)
+            if (t < mp) Y[t * NP + r] = (WT)v[t];
         }
       }
       __syncthreads();
