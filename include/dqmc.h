@@ -88,6 +88,7 @@ typedef struct {
 } dqmc_obs;
 
 typedef struct dqmc_batch dqmc_batch;   /* opaque host handle */
+typedef struct dqmc_graph dqmc_graph;   /* opaque recorded sweep of several batches */
 
 /* Device bytes one chain needs (the admission unit of a memory budget). */
 size_t dqmc_chain_bytes(const dqmc_model* m);
@@ -114,6 +115,32 @@ dqmc_status dqmc_sweep(dqmc_batch* b, int32_t n_sweeps, void* stream);
  * enqueued before any waits, the batches overlapping on the device through forked streams. */
 dqmc_status dqmc_sweep_multi(dqmc_batch* const* bs, const int32_t* n_sweeps, int32_t n,
                              void* stream);
+
+/* Re-initialise chains slots[0 .. n_slots-1] of an existing batch (continuous batching: a chain
+ * slot freed by a finished request takes a new one).  Each listed chain gets a new field and seed
+ * exactly as dqmc_init_chains would give chain i of a new batch (its result does not depend on
+ * the batch it runs in) and its counters restart at zero; other chains are untouched.
+ *   slots:  HOST int32 [n_slots], distinct, in [0, n_chains).
+ *   fields: DEVICE int8 [n_slots][n_slices][N] of +-1, or NULL to draw them from the seeds.
+ *   seeds:  HOST uint64 [n_slots].
+ * Waits for its own work; returns EINVAL for a bad slot list or field value.  Must not overlap
+ * a sweep of the same batch (order the two on one stream). */
+dqmc_status dqmc_init_slots(dqmc_batch* b, const int32_t* slots, int32_t n_slots,
+                            const int8_t* fields, const uint64_t* seeds, void* stream);
+
+/* One persistent launch in which chain c runs counts[c] sweeps (0 = idle this launch).
+ *   counts: DEVICE int32 [n_chains], read by the kernel when it runs (the caller keeps it
+ *           alive and unchanged until the launch has completed on the stream). */
+dqmc_status dqmc_sweep_counts(dqmc_batch* b, const int32_t* counts, void* stream);
+
+/* Record n_sweeps[i] sweeps of every batch bs[i] as one HIP graph of independent kernel nodes
+ * (batches of different lattices run side by side).  Each dqmc_graph_launch replays the
+ * recording and advances the chains by those sweeps, with the same results as the same calls
+ * of dqmc_sweep_multi.  The batches must outlive the graph; n >= 1. */
+dqmc_status dqmc_graph_create(dqmc_graph** out, dqmc_batch* const* bs, const int32_t* n_sweeps,
+                              int32_t n);
+dqmc_status dqmc_graph_launch(dqmc_graph* g, void* stream);
+dqmc_status dqmc_graph_destroy(dqmc_graph* g);
 
 /* Per-chain observables into obs (DEVICE [n_chains]); if green != NULL also both spins' G(0)
  * into green (DEVICE double [n_chains][2][N][N]).  Waits; returns ENUMERIC if any flag is set

@@ -1,0 +1,121 @@
+"""Per-model choice of the knobs that change speed but not the method.
+
+* Delay rank k (sites per delayed-update block).  Decisions do not depend on k, only rounding
+  and speed do, so k is chosen by timing: each candidate runs a few sweeps of a small batch and
+  the fastest wins.
+* FP32-wrap refresh interval.  Wrapping G in FP32 loses accuracy geometrically with the number
+  of wraps since the last FP64 refresh.  On fixed fields, the FP32-wrapped G after r wraps is
+  compared with the FP64 fresh G of the same slice (max |dG| over sampled slices and chains);
+  the largest r within the bound is chosen.
+
+Results are cached per model in a JSON file when a path is given.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import dqmc
+
+
+def _model_id(n_sites: int, n_slices: int, U: float, dtau: float, precision: str, extra="") -> str:
+    return f"N{n_sites}_L{n_slices}_U{U:g}_dt{dtau:g}_{precision}{extra}"
+
+
+class Autotuner:
+    def __init__(self, cache_path: Optional[str] = None, device="cuda:0"):
+        self.cache_path = cache_path
+        self.device = device
+        self.cache: Dict[str, dict] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    def _save(self):
+        if self.cache_path:
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+
+    def delay_rank(self, hopping, U, dtau, n_slices, stab_every, precision="fp64", refresh_every=0,
+                   candidates: Sequence[int] = (8, 16, 32), n_chains: int = 64, sweeps: int = 2,
+                   seed: int = 0x7A11) -> dict:
+        """Fastest delay rank among the candidates (the library clamps k to what its kernels
+        support; candidates that map to the same k are timed once)."""
+        T = np.asarray(hopping, dtype=np.float64)
+        key = _model_id(T.shape[0], n_slices, U, dtau, precision, f"_r{refresh_every}_k")
+        if key in self.cache:
+            return self.cache[key]
+        torch = dqmc._torch()
+        seeds = np.arange(n_chains, dtype=np.uint64) + np.uint64(seed)
+        timings, seen = {}, {}
+        for k in candidates:
+            m = dqmc.make_model(T, U, dtau, n_slices, stab_every, refresh_every=refresh_every,
+                                delay_rank=k, precision=precision)
+            b = dqmc.Batch(m, seeds, device=self.device)
+            eff = b.delay_rank
+            if eff in seen:
+                timings[k] = seen[eff]
+                b.close()
+                continue
+            b.sweep(1)
+            torch.cuda.synchronize(self.device)
+            t0 = time.perf_counter()
+            b.sweep(sweeps)
+            torch.cuda.synchronize(self.device)
+            dt = (time.perf_counter() - t0) / sweeps
+            seen[eff] = dt
+            timings[k] = dt
+            b.close()
+        best = min(timings, key=lambda k: timings[k])
+        rec = {"delay_rank": int(best), "seconds_per_sweep": {str(k): v for k, v in timings.items()}}
+        self.cache[key] = rec
+        self._save()
+        return rec
+
+    def refresh_interval(self, hopping, U, dtau, n_slices, fields, seeds, bound: float = 1e-5,
+                         candidates: Iterable[int] = (2, 3, 4, 5, 6, 8, 10),
+                         slices: Optional[Sequence[int]] = None, stab_every: int = 10) -> dict:
+        """Largest FP32-wrap refresh interval whose wrap error stays within `bound` on the given
+        fixed fields (int8 [chains][n_slices][N]); the error of r wraps from slice l is
+        max |G_fp32(l -> l + r) - G_fp64_fresh(l + r)| over chains and sampled slices."""
+        T = np.asarray(hopping, dtype=np.float64)
+        key = _model_id(T.shape[0], n_slices, U, dtau, "fp32_wrap", f"_b{bound:g}_refresh")
+        if key in self.cache:
+            return self.cache[key]
+        cands = sorted(int(r) for r in candidates if 1 <= int(r) <= n_slices)
+        if slices is None:
+            slices = sorted({0, n_slices // 3, (2 * n_slices) // 3})
+        # fresh G from UDT chains stabilised every stab_every slices in both precisions; the
+        # FP32 batch only differs in how it wraps
+        m64 = dqmc.make_model(T, U, dtau, n_slices, stab_every, precision="fp64")
+        m32 = dqmc.make_model(T, U, dtau, n_slices, stab_every, refresh_every=stab_every,
+                              precision="fp32_wrap")
+        b64 = dqmc.Batch(m64, seeds, fields, device=self.device)
+        b32 = dqmc.Batch(m32, seeds, fields, device=self.device)
+        errs = {}
+        for r in cands:
+            e = 0.0
+            for l in slices:
+                if l + r > n_slices:
+                    continue
+                g32 = b32.debug_green(l, r)
+                g64 = b64.debug_green(l + r, 0)
+                e = max(e, float((g32 - g64).abs().max().item()))
+            errs[r] = e
+        b64.close()
+        b32.close()
+        best = 1
+        for r in cands:              # the longest interval whose shorter ones all pass too
+            if errs[r] > bound:
+                break
+            best = r
+        rec = {"refresh_every": int(best), "bound": bound, "max_abs_dG": {str(r): v for r, v in errs.items()}}
+        self.cache[key] = rec
+        self._save()
+        return rec

@@ -94,13 +94,16 @@ __global__ __launch_bounds__(NT) void constants_kernel(int n, int np, double dta
 template <typename WT, bool SMALL>
 __global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
   extern __shared__ double lds[];
-  const int chain = blockIdx.x;
-  if (chain >= a.n_chains) return;
+  const int idx = blockIdx.x;
+  const int chain = a.slots ? a.slots[idx] : idx;
+  if (chain < 0 || chain >= a.n_chains) return;
+  const int n_sweeps = a.counts ? a.counts[chain] : a.n_sweeps;
+  if (a.op == OP_SWEEP && n_sweeps <= 0) return;
   Ctx<WT> c = make_ctx<WT, SMALL>(a, chain, lds);
   if (a.op == OP_INIT) {
     if (threadIdx.x == 0) {
       ChainStats* st = c.st;
-      st->seed = a.seeds[chain];
+      st->seed = a.seeds[idx];
       st->sweeps_done = st->attempted = st->accepted = st->near_ties = 0;
       st->max_drift = st->max_logdet_err = 0.0;
       st->logdet[0] = st->logdet[1] = 0.0;
@@ -109,9 +112,9 @@ __global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
       for (int k = 0; k < 16; ++k) st->ticks[k] = 0;
     }
     __syncthreads();
-    op_init(c, chain);
+    op_init(c, idx);
   } else if (a.op == OP_SWEEP) {
-    op_sweep(c, a.n_sweeps);
+    op_sweep(c, n_sweeps);
   } else if (a.op == OP_DEBUG_GREEN) {
     op_debug_green(c, chain);
   } else if (a.op == OP_DEBUG_RATIOS) {
@@ -124,7 +127,9 @@ __global__ __launch_bounds__(NT) void fast_sweep_kernel(KArgs a) {
   extern __shared__ double lds[];
   const int chain = blockIdx.x;
   if (chain >= a.n_chains) return;
-  fast::Fast<NP, WT, KB>::run(a, chain, lds);
+  const int n_sweeps = a.counts ? a.counts[chain] : a.n_sweeps;
+  if (n_sweeps <= 0) return;
+  fast::Fast<NP, WT, KB>::run(a, chain, n_sweeps, lds);
 }
 
 // ------------------------------------------------------------------------ measurements
@@ -247,6 +252,17 @@ struct dqmc_batch {
   KArgs args;   // base arguments (op fields filled per call)
   char* ws;
   size_t ws_bytes;
+  size_t c_seeds, c_slots, c_err;   // staging areas in the workspace
+};
+
+struct dqmc_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<KArgs> args;
+  ~dqmc_graph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
 };
 
 namespace {
@@ -257,7 +273,7 @@ struct Layout {
   size_t lds_bytes, fast_lds_bytes;
   // constants region (offsets from the workspace base)
   size_t c_expK, c_expKinv, c_expK32, c_expKinv32, c_T, c_eye, c_ones, c_A, c_E0, c_E1, c_seeds,
-      c_err, c_end;
+      c_slots, c_err, c_end;
   // per chain
   size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, stride;
 };
@@ -288,7 +304,9 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   if (n_chains < 0) return fail(DQMC_EINVAL, "n_chains must be >= 0");
   Layout L{};
   L.n = m->n_sites;
-  L.np = (L.n + 15) & ~15;
+  // padded size: a multiple of 16; up to 64 sites the padded sizes of the register/LDS sweep
+  // kernels (16, 32, 64)
+  L.np = L.n <= 16 ? 16 : L.n <= 32 ? 32 : L.n <= 64 ? 64 : (L.n + 15) & ~15;
   L.L = m->n_slices;
   L.precision = m->precision;
   int stab = m->stab_every;
@@ -351,6 +369,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   L.c_E0 = take(nn * 8);
   L.c_E1 = take(nn * 8);
   L.c_seeds = take((size_t)std::max(n_chains, 1) * 8);
+  L.c_slots = take((size_t)std::max(n_chains, 1) * 4);
   L.c_err = take(256);
   L.c_end = off;
   // chain
@@ -400,41 +419,79 @@ void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KAr
   a->o_left = L.o_left; a->o_work = L.o_work; a->o_xy = L.o_xy; a->o_stats = L.o_stats;
 }
 
-template <typename WT, bool SMALL>
-dqmc_status launch_chain(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
-  auto kern = chain_kernel<WT, SMALL>;
-  if (b->lds_bytes > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)b->lds_bytes));
-  hipLaunchKernelGGL(kern, dim3(b->n_chains), dim3(NT), b->lds_bytes, s, a);
-  HIP_TRY(hipGetLastError());
-  return DQMC_OK;
-}
+// The kernel a batch runs for an operation, and its LDS bytes.
+struct KernelRef {
+  const void* fn;
+  size_t lds;
+};
 
 template <int NP, typename WT, int KB>
-dqmc_status launch_fast_t(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
-  auto kern = fast_sweep_kernel<NP, WT, KB>;
-  const size_t bytes = fast::Fast<NP, WT, KB>::lds_bytes();
-  if (bytes > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  hipLaunchKernelGGL(kern, dim3(b->n_chains), dim3(NT), bytes, s, a);
-  HIP_TRY(hipGetLastError());
-  return DQMC_OK;
+KernelRef fast_ref() {
+  return {(const void*)fast_sweep_kernel<NP, WT, KB>, fast::Fast<NP, WT, KB>::lds_bytes()};
 }
 
 template <typename WT>
-dqmc_status launch_fast(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
-  if (b->np == 16) return launch_fast_t<16, WT, 8>(b, a, s);
-  if (b->np == 32) return b->K == 8 ? launch_fast_t<32, WT, 8>(b, a, s) : launch_fast_t<32, WT, 16>(b, a, s);
-  return b->K == 8 ? launch_fast_t<64, WT, 8>(b, a, s) : launch_fast_t<64, WT, 16>(b, a, s);
+KernelRef fast_ref(const dqmc_batch* b) {
+  if (b->np == 16) return fast_ref<16, WT, 8>();
+  if (b->np == 32) return b->K == 8 ? fast_ref<32, WT, 8>() : fast_ref<32, WT, 16>();
+  return b->K == 8 ? fast_ref<64, WT, 8>() : fast_ref<64, WT, 16>();
 }
 
-dqmc_status launch(const dqmc_batch* b, const KArgs& a, hipStream_t s) {
-  if (b->n_chains == 0) return DQMC_OK;
+KernelRef resolve(const dqmc_batch* b, int op) {
   const bool f32 = b->precision == DQMC_FP32_WRAP;
-  if (a.op == OP_SWEEP && b->fast) return f32 ? launch_fast<float>(b, a, s) : launch_fast<double>(b, a, s);
-  if (f32) return b->small ? launch_chain<float, true>(b, a, s) : launch_chain<float, false>(b, a, s);
-  return b->small ? launch_chain<double, true>(b, a, s) : launch_chain<double, false>(b, a, s);
+  if (op == OP_SWEEP && b->fast) return f32 ? fast_ref<float>(b) : fast_ref<double>(b);
+  const void* fn = f32 ? (b->small ? (const void*)chain_kernel<float, true> : (const void*)chain_kernel<float, false>)
+                       : (b->small ? (const void*)chain_kernel<double, true> : (const void*)chain_kernel<double, false>);
+  return {fn, b->lds_bytes};
+}
+
+dqmc_status prepare(const KernelRef& k) {
+  if (k.lds > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
+  return DQMC_OK;
+}
+
+// One workgroup of NT threads per chain (or per listed slot).
+dqmc_status launch(const dqmc_batch* b, const KArgs& a, hipStream_t s, int grid = -1) {
+  if (grid < 0) grid = b->n_chains;
+  if (grid == 0) return DQMC_OK;
+  const KernelRef k = resolve(b, a.op);
+  dqmc_status st = prepare(k);
+  if (st != DQMC_OK) return st;
+  KArgs arg = a;
+  void* params[] = {&arg};
+  HIP_TRY(hipLaunchKernel(k.fn, dim3(grid), dim3(NT), params, k.lds, s));
+  return DQMC_OK;
+}
+
+// Side streams for sweeping several batches at once, created on first use and kept for the
+// life of the process (default priority, non-blocking).
+struct SidePool {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  hipEvent_t fork = nullptr;
+  dqmc_status grow(int n) {
+    if (!fork && hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+      return fail(DQMC_EDEVICE, "side pool: event");
+    while ((int)streams.size() < n) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        return fail(DQMC_EDEVICE, "side pool: stream");
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        hipStreamDestroy(st);
+        return fail(DQMC_EDEVICE, "side pool: event");
+      }
+      streams.push_back(st);
+      events.push_back(ev);
+    }
+    return DQMC_OK;
+  }
+};
+
+SidePool& side_pool() {
+  static thread_local SidePool pool;
+  return pool;
 }
 
 }  // namespace
@@ -505,6 +562,7 @@ dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_ch
   b->n_chains = n_chains; b->precision = L.precision; b->small = L.small; b->lds_bytes = L.lds_bytes;
   b->fast = L.fast; b->fast_lds_bytes = L.fast_lds_bytes;
   b->ws = ws; b->ws_bytes = ws_bytes;
+  b->c_seeds = L.c_seeds; b->c_slots = L.c_slots; b->c_err = L.c_err;
   fill_args(L, m, ws, n_chains, &b->args);
   KArgs a = b->args;
   a.op = OP_INIT;
@@ -544,37 +602,59 @@ dqmc_status dqmc_sweep_multi(dqmc_batch* const* bs, const int32_t* n_sweeps, int
     if (!bs[i] || n_sweeps[i] < 0) return fail(DQMC_EINVAL, "bad batch entry");
   hipStream_t s = (hipStream_t)stream;
   if (n == 1) return dqmc_sweep(bs[0], n_sweeps[0], stream);
-  // fork: every batch on its own stream after an event on the caller's stream, then join
-  std::vector<hipStream_t> side(n, nullptr);
-  std::vector<hipEvent_t> done(n, nullptr);
-  hipEvent_t fork = nullptr;
-  dqmc_status st = DQMC_OK;
-  auto cleanup = [&]() {
-    for (int i = 0; i < n; ++i) {
-      if (done[i]) hipEventDestroy(done[i]);
-      if (side[i]) hipStreamDestroy(side[i]);
-    }
-    if (fork) hipEventDestroy(fork);
-  };
-  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(fork, s) != hipSuccess) {
-    cleanup();
-    return fail(DQMC_EDEVICE, "sweep_multi: fork event");
+  if (n == 0) return DQMC_OK;
+  // fork: every batch on a side stream after an event on the caller's stream, then join
+  SidePool& P = side_pool();
+  dqmc_status st = P.grow(n);
+  if (st != DQMC_OK) return st;
+  HIP_TRY(hipEventRecord(P.fork, s));
+  for (int i = 0; i < n; ++i) {
+    HIP_TRY(hipStreamWaitEvent(P.streams[i], P.fork, 0));
+    st = dqmc_sweep(bs[i], n_sweeps[i], P.streams[i]);
+    if (st != DQMC_OK) return st;
+    HIP_TRY(hipEventRecord(P.events[i], P.streams[i]));
+    HIP_TRY(hipStreamWaitEvent(s, P.events[i], 0));
   }
-  for (int i = 0; i < n && st == DQMC_OK; ++i) {
-    if (hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&done[i], hipEventDisableTiming) != hipSuccess ||
-        hipStreamWaitEvent(side[i], fork, 0) != hipSuccess) {
-      st = fail(DQMC_EDEVICE, "sweep_multi: stream setup");
-      break;
-    }
-    st = dqmc_sweep(bs[i], n_sweeps[i], side[i]);
-    if (st == DQMC_OK && (hipEventRecord(done[i], side[i]) != hipSuccess ||
-                          hipStreamWaitEvent(s, done[i], 0) != hipSuccess))
-      st = fail(DQMC_EDEVICE, "sweep_multi: join");
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_init_slots(dqmc_batch* b, const int32_t* slots, int32_t n_slots, const int8_t* fields,
+                            const uint64_t* seeds, void* stream) {
+  if (!b) return fail(DQMC_EINVAL, "batch is NULL");
+  if (n_slots < 0 || n_slots > b->n_chains) return fail(DQMC_EINVAL, "n_slots out of range");
+  if (n_slots == 0) return DQMC_OK;
+  if (!slots || !seeds) return fail(DQMC_EINVAL, "slots/seeds is NULL");
+  std::vector<char> seen(b->n_chains, 0);
+  for (int i = 0; i < n_slots; ++i) {
+    if (slots[i] < 0 || slots[i] >= b->n_chains) return fail(DQMC_EINVAL, "slot out of range");
+    if (seen[slots[i]]++) return fail(DQMC_EINVAL, "slot listed twice");
   }
-  cleanup();   // destroying a stream with pending work is deferred by the runtime
-  return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemsetAsync(b->ws + b->c_err, 0, sizeof(int), s));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->c_seeds, seeds, (size_t)n_slots * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->c_slots, slots, (size_t)n_slots * 4, hipMemcpyHostToDevice, s));
+  KArgs a = b->args;
+  a.op = OP_INIT;
+  a.gen_fields = fields ? 0 : 1;
+  a.fields_in = fields;
+  a.seeds = (const uint64_t*)(b->ws + b->c_seeds);
+  a.slots = (const int32_t*)(b->ws + b->c_slots);
+  dqmc_status st = launch(b, a, s, n_slots);
+  if (st != DQMC_OK) return st;
+  int err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, b->ws + b->c_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) return fail(DQMC_EINVAL, "fields must be +1 or -1");
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_sweep_counts(dqmc_batch* b, const int32_t* counts, void* stream) {
+  if (!b || !counts) return fail(DQMC_EINVAL, "batch/counts is NULL");
+  KArgs a = b->args;
+  a.op = OP_SWEEP;
+  a.n_sweeps = 0;
+  a.counts = counts;
+  return launch(b, a, (hipStream_t)stream);
 }
 
 dqmc_status dqmc_measure(dqmc_batch* b, dqmc_obs* obs, double* green, void* stream) {
@@ -670,6 +750,58 @@ dqmc_status dqmc_debug_mfma(const double* a64, const double* b64, double* out64,
   hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, a64, b64, out64,
                      a32, b32, out32);
   HIP_TRY(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_graph_create(dqmc_graph** out, dqmc_batch* const* bs, const int32_t* n_sweeps,
+                              int32_t n) {
+  if (!out) return fail(DQMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !bs || !n_sweeps) return fail(DQMC_EINVAL, "bad batch list");
+  for (int i = 0; i < n; ++i)
+    if (!bs[i] || n_sweeps[i] < 0) return fail(DQMC_EINVAL, "bad batch entry");
+  dqmc_graph* g = new (std::nothrow) dqmc_graph;
+  if (!g) return fail(DQMC_EDEVICE, "host allocation failed");
+  g->args.resize(n);
+  auto bail = [&](dqmc_status st) { delete g; return st; };
+  hipError_t e = hipGraphCreate(&g->graph, 0);
+  if (e != hipSuccess) return bail(fail(DQMC_EDEVICE, std::string("hipGraphCreate: ") + hipGetErrorString(e)));
+  for (int i = 0; i < n; ++i) {
+    if (n_sweeps[i] == 0 || bs[i]->n_chains == 0) continue;
+    KArgs& a = g->args[i];
+    a = bs[i]->args;
+    a.op = OP_SWEEP;
+    a.n_sweeps = n_sweeps[i];
+    const KernelRef k = resolve(bs[i], OP_SWEEP);
+    dqmc_status st = prepare(k);
+    if (st != DQMC_OK) return bail(st);
+    void* params[] = {&a};
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(k.fn);
+    p.gridDim = dim3(bs[i]->n_chains);
+    p.blockDim = dim3(NT);
+    p.sharedMemBytes = (unsigned)k.lds;
+    p.kernelParams = params;
+    p.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, g->graph, nullptr, 0, &p);
+    if (e != hipSuccess)
+      return bail(fail(DQMC_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e)));
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(fail(DQMC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)));
+  *out = g;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_graph_launch(dqmc_graph* g, void* stream) {
+  if (!g) return fail(DQMC_EINVAL, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_graph_destroy(dqmc_graph* g) {
+  delete g;
   return DQMC_OK;
 }
 

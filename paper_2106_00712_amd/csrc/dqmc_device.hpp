@@ -65,6 +65,8 @@ struct KArgs {
   int* err;             // device error word (field validation)
   const int8_t* fields_in;
   const uint64_t* seeds;
+  const int32_t* slots;   // init over a subset: block b initialises chain slots[b] from input b
+  const int32_t* counts;  // per-chain sweeps of this launch (NULL: n_sweeps for every chain)
   char* base;
   size_t stride;        // bytes per chain
   size_t o_fields, o_G64, o_Gw, o_stack, o_left, o_work, o_xy, o_stats;
@@ -877,7 +879,7 @@ __device__ void load_green(Ctx<WT>& c) {
 
 // ------------------------------------------------------------------------------ operations
 template <typename WT>
-__device__ void op_init(Ctx<WT>& c, int chain) {
+__device__ void op_init(Ctx<WT>& c, int idx) {
   const KArgs& a = *c.a;
   const int n = c.n, np = c.np, L = c.L, tid = threadIdx.x;
   // fields: drawn from the seed or copied and validated
@@ -892,7 +894,7 @@ __device__ void op_init(Ctx<WT>& c, int chain) {
         uint64_t word = (ee & 3) == 0 ? w.x0 : (ee & 3) == 1 ? w.x1 : (ee & 3) == 2 ? w.x2 : w.x3;
         v = (word & 1ull) ? 1 : -1;
       } else {
-        v = a.fields_in[((size_t)chain * L + l) * n + i];
+        v = a.fields_in[((size_t)idx * L + l) * n + i];
         if (v != 1 && v != -1) { atomicOr(a.err, 1); v = 1; }
       }
     }

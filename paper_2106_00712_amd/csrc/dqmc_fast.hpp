@@ -547,7 +547,7 @@ struct Fast {
     }
   }
 
-  static __device__ void run(const KArgs& a, int chain, double* lds) {
+  static __device__ void run(const KArgs& a, int chain, int n_sweeps, double* lds) {
     const int tid = threadIdx.x;
     Lds L = carve(lds);
     Regs R;
@@ -565,7 +565,7 @@ struct Fast {
     for (int e = tid; e < 2 * NN; e += NT) ((WT*)L.arena)[e] = (WT)c.G64[e];
     __syncthreads();
     PhaseClock clk, total;
-    for (int s = 0; s < a.n_sweeps; ++s) {
+    for (int s = 0; s < n_sweeps; ++s) {
       total.start();
       clk.start();
       park_green(c, L);

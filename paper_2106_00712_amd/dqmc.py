@@ -60,6 +60,11 @@ _SIGS = {
     "dqmc_last_error": (ctypes.c_char_p, []),
     "dqmc_batch_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "dqmc_init_slots": (_i32, [_vp, ctypes.POINTER(_i32), _i32, _vp, ctypes.POINTER(_u64), _vp]),
+    "dqmc_sweep_counts": (_i32, [_vp, _vp, _vp]),
+    "dqmc_graph_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32]),
+    "dqmc_graph_launch": (_i32, [_vp, _vp]),
+    "dqmc_graph_destroy": (_i32, [_vp]),
     "dqmc_debug_green": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "dqmc_debug_ratios": (_i32, [_vp, _i32, _vp, _vp]),
     "dqmc_debug_propagators": (_i32, [_vp, _vp, _vp]),
@@ -188,6 +193,39 @@ class Batch:
         with self.torch.cuda.device(self.device):
             _check(lib().dqmc_sweep(self._h, int(n_sweeps), _stream(stream, self.device)))
 
+    def init_slots(self, slots, seeds, fields=None, stream=None):
+        """Re-initialise the listed chains with new seeds (and fields, else drawn from the seeds)."""
+        torch = self.torch
+        slots = np.ascontiguousarray(np.asarray(slots, dtype=np.int32))
+        seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        if slots.shape != seeds.shape or slots.ndim != 1:
+            raise ValueError("slots and seeds must be 1-D and of equal length")
+        fptr, keep = ctypes.c_void_p(0), None
+        if fields is not None:
+            f = fields if isinstance(fields, torch.Tensor) else torch.as_tensor(
+                np.ascontiguousarray(np.asarray(fields, dtype=np.int8)))
+            keep = f.to(device=self.device, dtype=torch.int8).contiguous()
+            if tuple(keep.shape) != (len(slots), self.L, self.n):
+                raise ValueError(f"fields must be [{len(slots)}][{self.L}][{self.n}]")
+            fptr = _ptr(keep)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_init_slots(self._h, slots.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         len(slots), fptr,
+                                         seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                         _stream(stream, self.device)))
+        del keep
+
+    def sweep_counts(self, counts, stream=None):
+        """One launch in which chain c runs counts[c] sweeps (a device int32 tensor [n_chains])."""
+        torch = self.torch
+        if not isinstance(counts, torch.Tensor) or counts.dtype != torch.int32 or \
+                counts.device != self.device or tuple(counts.shape) != (self.n_chains,):
+            raise ValueError(f"counts must be an int32 tensor [{self.n_chains}] on {self.device}")
+        counts = counts.contiguous()
+        self._counts_keep = counts   # alive until the next launch of this batch is enqueued
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_sweep_counts(self._h, _ptr(counts), _stream(stream, self.device)))
+
     def measure(self, green: bool = False, stream=None):
         """Per-chain observables (numpy structured array) and optionally G(0) [c][2][N][N]."""
         torch = self.torch
@@ -264,6 +302,38 @@ def sweep_multi(batches, n_sweeps, stream=None):
     dev = batches[0].device
     with torch.cuda.device(dev):
         _check(lib().dqmc_sweep_multi(hs, ns, len(batches), _stream(stream, dev)))
+
+
+class Graph:
+    """A recorded sweep of several batches (one HIP graph); each launch() advances them."""
+
+    def __init__(self, batches, n_sweeps):
+        if not batches:
+            raise ValueError("need at least one batch")
+        self.batches = list(batches)
+        self.torch = batches[0].torch
+        self.device = batches[0].device
+        hs = (ctypes.c_void_p * len(batches))(*[b.handle.value for b in batches])
+        ns = (ctypes.c_int32 * len(batches))(*[int(x) for x in n_sweeps])
+        g = ctypes.c_void_p()
+        with self.torch.cuda.device(self.device):
+            _check(lib().dqmc_graph_create(ctypes.byref(g), hs, ns, len(batches)))
+        self._g = g
+
+    def launch(self, stream=None):
+        with self.torch.cuda.device(self.device):
+            _check(lib().dqmc_graph_launch(self._g, _stream(stream, self.device)))
+
+    def close(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            lib().dqmc_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_philox(key, ctr, n_blocks, device="cuda:0"):

@@ -52,7 +52,7 @@ def test_workspace_sizing_without_gpu(lib):
     per = dqmc.chain_bytes(m)
     assert per > 2 * 64 * 64 * 8          # at least both Green's functions
     a, b = dqmc.workspace_bytes(m, 1), dqmc.workspace_bytes(m, 256)
-    assert 255 * per <= b - a <= 255 * per + 256 * 8 + 256   # plus the seed table
+    assert 255 * per <= b - a <= 255 * per + 256 * (8 + 4) + 2 * 256   # plus seed and slot tables
     big = dqmc.make_model(di.square_hopping(20), 8.0, 0.1, 100, 10)
     assert dqmc.chain_bytes(big) > dqmc.chain_bytes(m)
 

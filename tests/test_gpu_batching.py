@@ -1,0 +1,134 @@
+"""Batching forms through the C ABI: slot re-initialisation, per-chain sweep counts, recorded
+graphs of several batches, and the continuous-batching server.  Every comparison is bitwise:
+a chain's trajectory depends only on its seed and starting field, never on its batch, slot,
+launch shape or neighbours."""
+import numpy as np
+import pytest
+
+import dqmc_inputs as di
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_00712_amd import dqmc
+    dqmc.lib()
+    return dqmc
+
+
+def _model(dq, w, **kw):
+    return dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, **kw)
+
+
+def _same(a_obs, a_fields, b_obs, b_fields):
+    keys = ("double_occ", "density", "kinetic", "logdet_up", "logdet_dn", "attempted",
+            "accepted", "sweeps_done", "flags")
+    for k in keys:
+        assert np.array_equal(a_obs[k], b_obs[k]), k
+    assert np.array_equal(a_fields, b_fields)
+
+
+@pytest.mark.parametrize("name", ["square8x8_U4_b4", "square4x4_U4_b2"])
+def test_init_slots_equals_a_new_batch(dq, name):
+    w = di.WORKLOADS[name]
+    m = _model(dq, w)
+    a = dq.Batch(m, w.seeds(6), w.fields(6))
+    a.sweep(2)
+    new_seeds = w.seeds(2, first=40)
+    a.init_slots([4, 1], new_seeds, w.fields(2, first=40))
+    a.sweep(3)
+    b = dq.Batch(m, new_seeds, w.fields(2, first=40))
+    b.sweep(3)
+    oa, ob = a.measure(), b.measure()
+    fa, fb = a.fields().cpu().numpy(), b.fields().cpu().numpy()
+    _same(oa[[4, 1]], fa[[4, 1]], ob, fb)
+    # untouched slots kept going from their own start
+    c = dq.Batch(m, w.seeds(6), w.fields(6))
+    c.sweep(5)
+    oc = c.measure()
+    _same(oa[[0, 2, 3, 5]], fa[[0, 2, 3, 5]], oc[[0, 2, 3, 5]], c.fields().cpu().numpy()[[0, 2, 3, 5]])
+
+
+def test_init_slots_from_seeds_and_errors(dq):
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    m = _model(dq, w)
+    a = dq.Batch(m, w.seeds(3))
+    a.init_slots([2], w.seeds(1, first=9))
+    b = dq.Batch(m, w.seeds(1, first=9))
+    assert np.array_equal(a.fields().cpu().numpy()[2], b.fields().cpu().numpy()[0])
+    with pytest.raises(dq.DqmcError):
+        a.init_slots([1, 1], w.seeds(2))
+    with pytest.raises(dq.DqmcError):
+        a.init_slots([3], w.seeds(1))
+    bad = np.ones((1, w.n_slices, w.n_sites), dtype=np.int8)
+    bad[0, 0, 0] = 0
+    with pytest.raises(dq.DqmcError):
+        a.init_slots([0], w.seeds(1), bad)
+    a.init_slots([0], w.seeds(1), np.ones((1, w.n_slices, w.n_sites), dtype=np.int8))  # recovers
+
+
+@pytest.mark.parametrize("name", ["square8x8_U4_b4", "square4x4_U4_b2"])
+def test_sweep_counts_equal_separate_sweeps(dq, name):
+    import torch
+    w = di.WORKLOADS[name]
+    m = _model(dq, w)
+    counts = [0, 1, 3, 2, 0, 4]
+    a = dq.Batch(m, w.seeds(6), w.fields(6))
+    a.sweep_counts(torch.tensor(counts, dtype=torch.int32, device=a.device))
+    oa, fa = a.measure(), a.fields().cpu().numpy()
+    for c, k in enumerate(counts):
+        b = dq.Batch(m, w.seeds(1, first=c), w.fields(1, first=c))
+        b.sweep(k)
+        _same(oa[[c]], fa[[c]], b.measure(), b.fields().cpu().numpy())
+
+
+def test_graph_replays_equal_eager_sweeps(dq):
+    """Two lattices in one recorded graph; every replay is checked against eager sweeps, with
+    eager work and synchronisation between replays."""
+    import torch
+    w8, w4 = di.WORKLOADS["square8x8_U4_b4"], di.WORKLOADS["square4x4_U4_b2"]
+    m8, m4 = _model(dq, w8), _model(dq, w4)
+    g8, g4 = dq.Batch(m8, w8.seeds(4), w8.fields(4)), dq.Batch(m4, w4.seeds(3), w4.fields(3))
+    e8, e4 = dq.Batch(m8, w8.seeds(4), w8.fields(4)), dq.Batch(m4, w4.seeds(3), w4.fields(3))
+    graph = dq.Graph([g8, g4], [1, 2])
+    for rep in range(3):
+        graph.launch()
+        dq.sweep_multi([e8, e4], [1, 2])
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()     # unrelated eager work in between
+        for g, e in ((g8, e8), (g4, e4)):
+            _same(g.measure(), g.fields().cpu().numpy(), e.measure(), e.fields().cpu().numpy())
+    graph.close()
+
+
+def test_padded_small_lattice_uses_fast_path(dq):
+    w = di.Workload("square6x6_U4_b2", 7, "square", 6, 4.0, 2.0, 0.1, 2, 2, 10)
+    b = dq.Batch(_model(dq, w), w.seeds(2), w.fields(2))
+    assert b.variant == 2
+
+
+def _serve(dq, reqs, capacity, tick, precision="fp64"):
+    from paper_2106_00712_amd.serving import GpuExecutor, Server
+    ex = GpuExecutor(di.square_hopping, U=4.0, dtau=0.1, stab_every=10,
+                     refresh_every=4 if precision == "fp32_wrap" else 0)
+    srv = Server(ex, hbm_budget=8 << 30, tick_sweeps=tick, pool_capacity=capacity,
+                 precision=precision, keep_fields=True)
+    return srv.run(reqs, realtime=False)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_wrap"])
+def test_serving_result_same_alone_and_in_the_mix(dq, precision):
+    from paper_2106_00712_amd.serving import poisson_requests, Request
+    reqs = poisson_requests(14, rate=2000.0, seed=7, Ls=(4, 6, 8), betas=(1.0, 2.0), sweeps=(2, 9))
+    mixed = {r.rid: r for r in _serve(dq, reqs, capacity=3, tick=2, precision=precision)}
+    assert sorted(mixed) == list(range(14))
+    for q in reqs[:4] + reqs[-2:]:
+        alone = _serve(dq, [Request(q.rid, q.L, q.beta, q.sweeps, q.seed)], capacity=1, tick=5,
+                       precision=precision)[0]
+        m = mixed[q.rid]
+        assert int(m.obs["sweeps_done"]) == q.sweeps
+        _same(np.array([alone.obs]), alone.fields, np.array([m.obs]), m.fields)

@@ -220,3 +220,36 @@ def test_rejects_small_workspace(dq):
     with pytest.raises(dq.DqmcError) as e:
         dq.Batch(m, w.seeds(2), w.fields(2), workspace=ws)
     assert e.value.status == -2
+
+
+# ------------------------------------------------------------------ other sizes
+SQUARE6 = di.Workload("square6x6_U4_b2", 7, "square", 6, 4.0, 2.0, 0.1, 2, 2, 10)
+
+
+def test_trajectory_parity_square6x6_padded(dq):
+    """N = 36 runs in the N <= 64 kernels padded to 64 (partial blocks, identity-padded inverse)."""
+    b, _ = _trajectory_check(dq, SQUARE6, 2, 3)
+    assert b.variant == 2
+
+
+def test_trajectory_parity_honeycomb6x6_generic(dq):
+    """N = 72 (padded to 80) runs in the generic kernels."""
+    b, _ = _trajectory_check(dq, di.WORKLOADS["honeycomb6x6_U3_b6"], 1, 1)
+    assert b.variant in (0, 1)
+
+
+@pytest.mark.parametrize("name,cases", [
+    ("honeycomb12x12_U3_b6", [(0, 0), (30, 1), (60, 0)]),
+    ("square20x20_U8_b10", [(0, 0), (50, 1), (100, 0)]),
+])
+def test_large_lattice_green_parity(dq, name, cases):
+    """Fresh G and one wrap at N = 288 and N = 400 to 1e-10 relative (longer wrap sequences at
+    these sizes differ between correct evaluations by more than that)."""
+    w = di.WORKLOADS[name]
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    b = dq.Batch(m, w.seeds(1), w.fields(1))
+    _, oc = oracle_for(w, 1)
+    for sl, nw in cases:
+        g = b.debug_green(sl, nw).cpu().numpy()
+        ref = oc.debug_green(sl, nw)
+        assert rel(g, ref) < 1e-10, (name, sl, nw, rel(g, ref))
