@@ -57,6 +57,25 @@ def algorithmic_flops(N: int, L: int, n_s: int, acc: float) -> dict:
     return parts
 
 
+def row_rooflines(fl: dict, share: dict, t_launch: float, n_chains: int, peak: float) -> dict:
+    """Each step of the path against the FP64 matrix peak: its algorithmic FLOP (per chain-sweep,
+    times the chains of one launch) over the time the in-kernel phase counters give it."""
+    groups = {
+        "wrap": (["wrap"], ["wrap"]),
+        "ratio_accept": ([], ["decide"]),
+        "update": (["update"], ["panel", "flush"]),
+        "stabilisation": (["chain", "qr", "fresh_g"], ["right_stack", "left_udt", "fresh_g"]),
+    }
+    out = {}
+    for row, (fparts, phases) in groups.items():
+        t = sum(share.get(p, 0.0) for p in phases) * t_launch
+        f = sum(fl[p] for p in fparts) * n_chains
+        out[row] = {"ms": t * 1e3, "share": t / t_launch if t_launch else None,
+                    "tflops": (f / t / 1e12) if (t > 0 and f > 0) else None,
+                    "frac": (f / t / peak) if (t > 0 and f > 0) else None}
+    return out
+
+
 def kernel_sha() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -187,6 +206,7 @@ def main():
                      "launch_ms": t_launch * 1e3,
                      "flop_per_chain_sweep": fl, "acceptance": acc},
         "phase_share": r64["phase_share"],
+        "rows": row_rooflines(fl, r64["phase_share"], t_launch, w.n_chains, PEAK_FP64_MFMA),
         "init_ms": r64["init_ms"],
         "max_drift_fp64": float(o["max_drift"].max()),
         "flags": int(np.bitwise_or.reduce(o["flags"])),

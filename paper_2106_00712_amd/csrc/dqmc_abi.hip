@@ -332,7 +332,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
     L.lds_bytes = small_bytes(L.K);
   } else {
     L.K = std::max(4, std::min(kreq, 32));
-    L.lds_bytes = lds_vec_doubles(L.np, L.K) * sizeof(double);
+    L.lds_bytes = (lds_vec_doubles(L.np, L.K) + TG_STAGE_DOUBLES) * sizeof(double);
     if (L.lds_bytes > (size_t)lds_limit) return fail(DQMC_EINVAL, "n_sites too large for LDS vectors");
   }
   // fast sweep path: padded size 16, 32 or 64, block size 8 or 16 sites

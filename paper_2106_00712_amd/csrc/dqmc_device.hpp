@@ -129,6 +129,96 @@ __device__ __forceinline__ void wg_gemm(int nb, int M, int Nc, int K, const T* A
   }
 }
 
+// ------------------------------------------------------------------------------ tiled products
+// Matrix products for chains whose matrices live in the chain's workspace (N > 64): operands
+// are read from HBM/L2 in coalesced 16-wide K panels, staged through a double-buffered LDS
+// area, and multiplied on the matrix cores in 64 x 64 output macro-tiles (each wavefront a
+// 32 x 32 quadrant of 2 x 2 MFMA tiles).
+constexpr int TG_M = 64;    // macro-tile rows / columns
+constexpr int TG_K = 16;    // K panel
+// LDS staging in doubles: two buffers of A (K-major, TG_K x TG_M) and B (TG_K x TG_M)
+constexpr int TG_STAGE_DOUBLES = 4 * TG_K * TG_M;
+
+// C_b(i, j) = sum_{k < K} A_b(i, k) B_b(k, j) for b < nb, i < M, j < Nc (M, Nc multiples of 16),
+// A_b(i, k) = A_b[i sai + k sak], B_b(k, j) = B_b[k sbk + j sbj] with unit stride in one of
+// each pair (row- or column-major operands).  epi(b, i, j, value) is called once per output
+// element by the lane that owns it.  All NT threads of the workgroup take part.
+template <typename T, typename Epi>
+__device__ __forceinline__ void gemm_tiled(double* stage, int nb, int M, int Nc, int K, const T* A0, const T* A1,
+                           int sai, int sak, const T* B0, const T* B1, int sbk, int sbj, Epi epi) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int mt = (M + TG_M - 1) / TG_M, nt = (Nc + TG_M - 1) / TG_M, kc = (K + TG_K - 1) / TG_K;
+  T* As[2] = {(T*)stage, (T*)stage + TG_K * TG_M};
+  T* Bs[2] = {(T*)stage + 2 * TG_K * TG_M, (T*)stage + 3 * TG_K * TG_M};
+  const bool a_rows = (sak == 1);    // A contiguous along k (row-major), else along i
+  const bool b_rows = (sbj == 1);    // B contiguous along j (row-major), else along k
+  // each thread moves 4 consecutive elements of each panel per chunk
+  const int a_i = a_rows ? (tid >> 2) : ((tid & 15) * 4), a_k = a_rows ? ((tid & 3) * 4) : (tid >> 4);
+  const int b_k = b_rows ? (tid >> 4) : ((tid & 3) * 4), b_j = b_rows ? ((tid & 15) * 4) : (tid >> 2);
+  for (int t = 0; t < nb * mt * nt; ++t) {
+    const int b = t / (mt * nt), tt = t - b * (mt * nt);
+    const int m0 = (tt / nt) * TG_M, n0 = (tt - (tt / nt) * nt) * TG_M;
+    const T* A = b ? A1 : A0;
+    const T* B = b ? B1 : B0;
+    T ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = m0 + a_i + (a_rows ? 0 : u), k = k0 + a_k + (a_rows ? u : 0);
+        ra[u] = (i < M && k < K) ? A[(size_t)i * sai + (size_t)k * sak] : (T)0;
+        const int kk = k0 + b_k + (b_rows ? 0 : u), j = n0 + b_j + (b_rows ? u : 0);
+        rb[u] = (kk < K && j < Nc) ? B[(size_t)kk * sbk + (size_t)j * sbj] : (T)0;
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        As[buf][(a_k + (a_rows ? u : 0)) * TG_M + a_i + (a_rows ? 0 : u)] = ra[u];
+        Bs[buf][(b_k + (b_rows ? 0 : u)) * TG_M + b_j + (b_rows ? u : 0)] = rb[u];
+      }
+    };
+    typename acc4<T>::type acc[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[r][q] = typename acc4<T>::type{0, 0, 0, 0};
+    const bool live_r[2] = {m0 + wr * 32 < M, m0 + wr * 32 + 16 < M};
+    const bool live_c[2] = {n0 + wc * 32 < Nc, n0 + wc * 32 + 16 < Nc};
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < kc; ++c) {
+      const int cur = c & 1;
+      if (c + 1 < kc) load((c + 1) * TG_K);
+      if (live_r[0] && live_c[0]) {
+#pragma unroll
+        for (int s = 0; s < TG_K / 4; ++s) {
+          const int kr = (4 * s + lk) * TG_M;
+          const T a0 = As[cur][kr + wr * 32 + li], a1 = As[cur][kr + wr * 32 + 16 + li];
+          const T b0 = Bs[cur][kr + wc * 32 + li], b1 = Bs[cur][kr + wc * 32 + 16 + li];
+          acc[0][0] = mfma(a0, b0, acc[0][0]);
+          if (live_c[1]) acc[0][1] = mfma(a0, b1, acc[0][1]);
+          if (live_r[1]) acc[1][0] = mfma(a1, b0, acc[1][0]);
+          if (live_r[1] && live_c[1]) acc[1][1] = mfma(a1, b1, acc[1][1]);
+        }
+      }
+      if (c + 1 < kc) store(cur ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!(live_r[r] && live_c[q])) continue;
+        const int i0 = m0 + wr * 32 + r * 16, j0 = n0 + wc * 32 + q * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) epi(b, i0 + out_row<T>(v, lane), j0 + li, acc[r][q][v]);
+      }
+  }
+}
+
 // ------------------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
@@ -237,6 +327,7 @@ struct Ctx {
   double *cfu, *cfd, *ublk;  // [K]
   int *site, *sblk, *cnt;   // [K], [K], [4]
   double* misc;       // [16]
+  double* stage;      // LDS staging of the tiled products (matrices in the workspace), else NULL
   Red red;
 };
 
@@ -290,6 +381,11 @@ __device__ inline Ctx<WT> make_ctx(const KArgs& a, int chain, double* lds) {
     c.w2 = c.w1 + nn;
     c.xy = (WT*)(cb + a.o_xy);
   }
+  c.stage = nullptr;
+  if (!SMALL) {
+    c.stage = p;
+    p += TG_STAGE_DOUBLES;
+  }
   c.red.v = p; p += 2 * NW;
   c.misc = p; p += 16;
   c.vd = p; p += np;
@@ -313,6 +409,16 @@ __device__ inline Ctx<WT> make_ctx(const KArgs& a, int chain, double* lds) {
   c.rank = ip; ip += np;
   c.red.parity = 0;
   return c;
+}
+
+// Products of the generic path: tiled through the LDS staging area when the matrices live in the
+// workspace, straight from LDS otherwise.
+template <typename T, typename WT, typename Epi>
+__device__ __forceinline__ void ctx_gemm(Ctx<WT>& c, int nb, int M, int Nc, int K, const T* A0,
+                                         const T* A1, int sai, int sak, const T* B0, const T* B1,
+                                         int sbk, int sbj, Epi epi) {
+  if (c.stage) gemm_tiled<T>(c.stage, nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
+  else wg_gemm<T>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
 }
 
 // ------------------------------------------------------------------------------ helpers
@@ -350,22 +456,43 @@ __device__ inline void slice_scales(Ctx<WT>& c, int li) {
 }
 
 // ------------------------------------------------------------------------------ QR / UDT
+// Sum over the 64 lanes by DPP (row_shr 1, 2, 4, 8 inclusive scans within each 16-lane row,
+// then row_bcast:15 and row_bcast:31 carry the row totals up; lane 63 holds the sum).
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double x) {
+  x += dpp_d<0x111>(x);
+  x += dpp_d<0x112>(x);
+  x += dpp_d<0x114>(x);
+  x += dpp_d<0x118>(x);
+  x += dpp_d<0x142, 0xa>(x);
+  x += dpp_d<0x143, 0xc>(x);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // Column-pivoted Householder QR (Golub & Van Loan, Alg. 5.4.1) of the n x n leading block of
-// X (leading dimension np), with implicit pivoting: columns stay in place, ordv[j] is the
-// column chosen at step j, rank[c] the step at which column c was chosen.  On return row j of
-// column ordv[j'] (j <= j') holds R[j][j']; column ordv[j] below row j holds the Householder
-// vector v_j (v_j[j] in vd[j]) and bt[j] = beta_j = 2 / (v_j^T v_j).  Pivot = the remaining
-// column of largest norm over the remaining rows, recomputed exactly at every step.
+// X stored column-major (element (r, col) at X[col * np + r]), with implicit pivoting: columns
+// stay in place, ordv[j] is the column chosen at step j, rank[col] the step at which column col
+// was chosen.  On return row j of column ordv[j'] (j <= j') holds R[j][j']; column ordv[j] below
+// row j holds the Householder vector v_j (v_j[j] in vd[j]) and bt[j] = beta_j = 2 / (v_j^T v_j).
+// Pivot = the remaining column of largest norm over the remaining rows, recomputed exactly at
+// every step.  One wavefront per column: every access runs down a contiguous column.
 template <typename WT>
-__device__ void wg_qrp(Ctx<WT>& c, double* X) {
-  const int n = c.n, np = c.np, tid = threadIdx.x;
-  const int g = tid >> 2, q = tid & 3;
+__device__ __forceinline__ void wg_qrp(Ctx<WT>& c, double* X) {
+  const int n = c.n, np = c.np, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* vb = c.sc;   // the pivot column of the current step (LDS)
   for (int k = tid; k < n; k += NT) c.rank[k] = -1;
-  for (int col = g; col < n; col += NT / 4) {
+  for (int col = wave; col < n; col += NW) {
     double s = 0;
-    for (int r = q; r < n; r += 4) { double x = X[r * np + col]; s += x * x; }
-    s = group4_sum(s);
-    if (q == 0) c.nrm[col] = s;
+    for (int r = lane; r < n; r += 64) { const double x = X[(size_t)col * np + r]; s += x * x; }
+    s = wave_sum_dpp(s);
+    if (lane == 0) c.nrm[col] = s;
   }
   double alpha_prev = 0, v0_prev = 0, beta_prev = 0;
   int p_prev = -1;
@@ -373,89 +500,109 @@ __device__ void wg_qrp(Ctx<WT>& c, double* X) {
   for (int j = 0; j < n; ++j) {
     // publish the previous step's R diagonal and reflector (column p_prev is no longer read)
     if (tid == 0 && p_prev >= 0) {
-      X[(j - 1) * np + p_prev] = alpha_prev;
+      X[(size_t)p_prev * np + (j - 1)] = alpha_prev;
       c.vd[j - 1] = v0_prev;
       c.bt[j - 1] = beta_prev;
     }
-    // pivot: largest remaining column norm
     double key = -1.0;
     int idx = -1;
     for (int k = tid; k < n; k += NT) {
       if (c.rank[k] < 0) {
-        double v = c.nrm[k];
+        const double v = c.nrm[k];
         if (idx < 0 || v > key) { key = v; idx = k; }
       }
     }
     const int p = wg_argmax(key, idx, c.red);
-    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; }
-    const double xj = X[j * np + p];
+    const double* xp = X + (size_t)p * np;
+    const double xj = xp[j];
     const double nx = sqrt(c.nrm[p]);
     const double alpha = (xj >= 0.0) ? -nx : nx;
     const double beta = (nx > 0.0) ? 1.0 / (alpha * (alpha - xj)) : 0.0;
     const double v0 = xj - alpha;
+    for (int r = j + tid; r < n; r += NT) vb[r] = (r == j) ? v0 : xp[r];
+    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; }
+    __syncthreads();
     // apply H_j = I - beta v v^T to every remaining column, recomputing its norm below row j
-    for (int k0 = 0; k0 < n; k0 += NT / 4) {
-      const int col = k0 + g;
-      const bool act = (col < n) && (col != p) && (c.rank[col] < 0);
-      if (!__builtin_expect(act, 1)) continue;
+    for (int col = wave; col < n; col += NW) {
+      if (col == p || c.rank[col] >= 0) continue;
+      double* xc = X + (size_t)col * np;
       double w = 0;
-      for (int r = j + q; r < n; r += 4) {
-        double vr = (r == j) ? v0 : X[r * np + p];
-        w += vr * X[r * np + col];
-      }
-      w = group4_sum(w) * beta;
+      for (int r = j + lane; r < n; r += 64) w += vb[r] * xc[r];
+      w = wave_sum_dpp(w) * beta;
       double s2 = 0;
-      for (int r = j + q; r < n; r += 4) {
-        double vr = (r == j) ? v0 : X[r * np + p];
-        double x = X[r * np + col] - w * vr;
-        X[r * np + col] = x;
+      for (int r = j + lane; r < n; r += 64) {
+        const double x = xc[r] - w * vb[r];
+        xc[r] = x;
         if (r > j) s2 += x * x;
       }
-      s2 = group4_sum(s2);
-      if (q == 0) c.nrm[col] = s2;
+      s2 = wave_sum_dpp(s2);
+      if (lane == 0) c.nrm[col] = s2;
     }
     alpha_prev = alpha; v0_prev = v0; beta_prev = beta; p_prev = p;
     __syncthreads();
   }
   if (tid == 0 && p_prev >= 0) {
-    X[(n - 1) * np + p_prev] = alpha_prev;
+    X[(size_t)p_prev * np + (n - 1)] = alpha_prev;
     c.vd[n - 1] = v0_prev;
     c.bt[n - 1] = beta_prev;
   }
   __syncthreads();
 }
 
-// After wg_qrp: U = Q S (columns in pivot order, S = sign(diag R)) into Ud (np x np, zero
-// padded), d_j = |R_jj| into dd (1 on padding), then X <- T' = D^{-1} S R P^T in original
-// column order (zero padded): T'[a][col] = s_a X[a][col] / d_a when rank[col] >= a.
-template <typename WT>
-__device__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* flags) {
-  const int n = c.n, np = c.np, tid = threadIdx.x;
-  const int g = tid >> 2, q = tid & 3;
-  // Q column jj = H_0 H_1 ... H_jj e_jj (later reflectors do not touch e_jj)
-  for (int jj = g; jj < np; jj += NT / 4) {
-    for (int r = q; r < np; r += 4) Ud[r * np + jj] = (r == jj && jj < n) ? 1.0 : 0.0;
-    if (jj >= n) continue;
-    for (int j = jj; j >= 0; --j) {
-      const int p = c.ordv[j];
-      double w = 0;
-      for (int r = j + q; r < n; r += 4) {
-        double vr = (r == j) ? c.vd[j] : X[r * np + p];
-        w += vr * Ud[r * np + jj];
-      }
-      w = group4_sum(w) * c.bt[j];
-      for (int r = j + q; r < n; r += 4) {
-        double vr = (r == j) ? c.vd[j] : X[r * np + p];
-        Ud[r * np + jj] -= w * vr;
+// Column jj of Q = H_0 H_1 ... H_jj e_jj (later reflectors do not touch e_jj), one wavefront per
+// column with the column in registers (element r = lane + 64 t), written to Ud (row-major).
+template <int CR>
+__device__ __forceinline__ void q_columns(int n, int np, const double* X, const double* vd,
+                                          const double* bt, const int* ordv, double* Ud) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jj = wave; jj < np; jj += NW) {
+    double q[CR];
+#pragma unroll
+    for (int t = 0; t < CR; ++t) q[t] = (lane + 64 * t == jj && jj < n) ? 1.0 : 0.0;
+    if (jj < n) {
+      for (int j = jj; j >= 0; --j) {
+        const double* v = X + (size_t)ordv[j] * np;
+        const double v0 = vd[j];
+        double w = 0;
+#pragma unroll
+        for (int t = 0; t < CR; ++t) {
+          const int r = lane + 64 * t;
+          if (r >= j && r < n) w += (r == j ? v0 : v[r]) * q[t];
+        }
+        w = wave_sum_dpp(w) * bt[j];
+#pragma unroll
+        for (int t = 0; t < CR; ++t) {
+          const int r = lane + 64 * t;
+          if (r >= j && r < n) q[t] -= w * (r == j ? v0 : v[r]);
+        }
       }
     }
+#pragma unroll
+    for (int t = 0; t < CR; ++t) {
+      const int r = lane + 64 * t;
+      if (r < np) Ud[(size_t)r * np + jj] = q[t];
+    }
   }
+}
+
+// After wg_qrp: U = Q S (columns in pivot order, S = sign(diag R)) into Ud (np x np row-major,
+// zero padded), d_j = |R_jj| into dd (1 on padding), then X <- T' = D^{-1} S R P^T in original
+// column order, still column-major (zero padded): T'[a][col] = s_a R(a, col) / d_a when
+// rank[col] >= a.
+template <typename WT>
+__device__ __forceinline__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* flags) {
+  const int n = c.n, np = c.np, tid = threadIdx.x;
+  if (np <= 128) q_columns<2>(n, np, X, c.vd, c.bt, c.ordv, Ud);
+  else if (np <= 256) q_columns<4>(n, np, X, c.vd, c.bt, c.ordv, Ud);
+  else if (np <= 512) q_columns<8>(n, np, X, c.vd, c.bt, c.ordv, Ud);
+  else if (np <= 1024) q_columns<16>(n, np, X, c.vd, c.bt, c.ordv, Ud);
+  else q_columns<32>(n, np, X, c.vd, c.bt, c.ordv, Ud);
   __syncthreads();
   // signs and scales
   for (int jj = tid; jj < np; jj += NT) {
     double dj = 1.0, sj = 1.0;
     if (jj < n) {
-      double rjj = X[jj * np + c.ordv[jj]];
+      const double rjj = X[(size_t)c.ordv[jj] * np + jj];
       dj = fabs(rjj);
       sj = (rjj < 0.0) ? -1.0 : 1.0;
       if (!(dj > 0.0)) atomicOr(flags, FLAG_SINGULAR);
@@ -465,11 +612,11 @@ __device__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* f
   }
   __syncthreads();
   for (int e = tid; e < np * np; e += NT) {
-    int r = e / np, col = e - r * np;
+    const int r = e / np, col = e - r * np;
     if (col < n) Ud[e] *= c.dtmp[col];
   }
   for (int e = tid; e < np * np; e += NT) {
-    int aa = e / np, col = e - aa * np;
+    const int col = e / np, aa = e - col * np;    // column-major walk
     double v = 0.0;
     if (aa < n && col < n && c.rank[col] >= aa) v = c.dtmp[aa] * X[e] / dd[aa];
     X[e] = v;
@@ -483,7 +630,7 @@ __device__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* f
 // then UDT of the result: Ud Diag(dd) (T' Ts) -> (Ud, dd, Td).  Ts may be the identity.
 // Work matrices w1/w2 are used; the result ends up in the destination buffers.
 template <typename WT>
-__device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const double* Us,
+__device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const double* Us,
                          const double* ds, const double* Ts, double* Ud, double* dd, double* Td) {
   const KArgs& a = *c.a;
   const int np = c.np, n = c.n;
@@ -494,10 +641,11 @@ __device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const
     __syncthreads();
     for (int l = lo + 1; l <= hi; ++l) {
       const int8_t* fl = c.f + (size_t)(l - 1) * np;
-      wg_gemm<double>(1, np, np, np, a.expK, a.expK, np, 1, cur, cur, np, 1,
+      const bool last = (l == hi);   // the last product goes out column-major for the QR
+      ctx_gemm<double>(c, 1, np, np, np, a.expK, a.expK, np, 1, cur, cur, np, 1,
                       [&](int, int i, int j, double v) {
                         double s = (i < n) ? vfac(a, spin, fl[i]) : 1.0;
-                        nxt[i * np + j] = s * v;
+                        nxt[last ? (size_t)j * np + i : (size_t)i * np + j] = s * v;
                       });
       __syncthreads();
       double* t = cur; cur = nxt; nxt = t;
@@ -516,10 +664,11 @@ __device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const
     for (int l = hi; l >= lo + 1; --l) {
       const int8_t* fn = (l - 1 >= lo + 1) ? c.f + (size_t)(l - 2) * np : nullptr;
       // expK^T as the A operand: A(i,k) = expK[k*np + i]
-      wg_gemm<double>(1, np, np, np, a.expK, a.expK, 1, np, cur, cur, np, 1,
+      const bool last = (l == lo + 1);
+      ctx_gemm<double>(c, 1, np, np, np, a.expK, a.expK, 1, np, cur, cur, np, 1,
                       [&](int, int i, int j, double v) {
                         double s = (fn && i < n) ? vfac(a, spin, fn[i]) : 1.0;
-                        nxt[i * np + j] = s * v;
+                        nxt[last ? (size_t)j * np + i : (size_t)i * np + j] = s * v;
                       });
       __syncthreads();
       double* t = cur; cur = nxt; nxt = t;
@@ -527,8 +676,8 @@ __device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const
   }
   wg_qrp(c, cur);
   udt_finish(c, cur, Ud, dd, &c.st->flags);
-  // Td = T' Ts  (cur now holds T')
-  wg_gemm<double>(1, np, np, np, cur, cur, np, 1, Ts, Ts, np, 1,
+  // Td = T' Ts  (cur now holds T', column-major)
+  ctx_gemm<double>(c, 1, np, np, np, cur, cur, 1, np, Ts, Ts, np, 1,
                   [&](int, int i, int j, double v) { Td[i * np + j] = v; });
   __syncthreads();
 }
@@ -536,10 +685,12 @@ __device__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const
 // ------------------------------------------------------------------------------ fresh G
 // Gauss-Jordan elimination with partial (implicit) row pivoting on M (n x n, leading dim np),
 // applied to the right-hand side Z (np columns).  On return w_dst = M^{-1} Z with its rows
-// scaled by rs[] (rs may be null), and the log|det M| is returned to all threads.
+// scaled by rs[] (rs may be null), and the log|det M| is returned to all threads.  The pivot
+// row is staged in LDS; one wavefront per eliminated row, its lanes along the row.
 template <typename WT>
-__device__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double* Z, double* dst, const double* rs) {
-  const int n = c.n, np = c.np, tid = threadIdx.x;
+__device__ __forceinline__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double* Z, double* dst, const double* rs) {
+  const int n = c.n, np = c.np, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* prow = c.sr;   // [2 np]: M[p][j+1 .. n-1] then Z[p][0 .. np-1]
   for (int k = tid; k < np; k += NT) c.rank[k] = -1;   // rank[row] = step at which row pivoted
   __syncthreads();
   double logabs = 0.0;
@@ -548,39 +699,36 @@ __device__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double* Z, double* dst,
     int idx = -1;
     for (int r = tid; r < n; r += NT) {
       if (c.rank[r] < 0) {
-        double v = fabs(M[r * np + j]);
+        const double v = fabs(M[(size_t)r * np + j]);
         if (idx < 0 || v > key) { key = v; idx = r; }
       }
     }
     const int p = wg_argmax(key, idx, c.red);
-    const double piv = M[p * np + j];
+    const double piv = M[(size_t)p * np + j];
     logabs += log(fabs(piv));
-    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; c.dtmp[j] = piv; }
-    const double inv = 1.0 / piv;
-    // eliminate column j from every other row with the (unscaled) pivot row p
     const int wM = n - j - 1;   // columns j+1 .. n-1 of M
-    const int tot = n * (wM + np);
-    for (int e = tid; e < tot; e += NT) {
-      int r = e / (wM + np), cc = e - r * (wM + np);
+    for (int e = tid; e < wM + np; e += NT)
+      prow[e] = (e < wM) ? M[(size_t)p * np + j + 1 + e] : Z[(size_t)p * np + (e - wM)];
+    if (tid == 0) { c.rank[p] = j; c.ordv[j] = p; c.dtmp[j] = piv; }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int r = wave; r < n; r += NW) {
       if (r == p) continue;
-      double fct = M[r * np + j] * inv;
+      double* mr = M + (size_t)r * np;
+      const double fct = mr[j] * inv;
       if (fct == 0.0) continue;
-      if (cc < wM) {
-        int col = j + 1 + cc;
-        M[r * np + col] -= fct * M[p * np + col];
-      } else {
-        int col = cc - wM;
-        Z[r * np + col] -= fct * Z[p * np + col];
-      }
+      for (int e = lane; e < wM; e += 64) mr[j + 1 + e] -= fct * prow[e];
+      double* zr = Z + (size_t)r * np;
+      for (int e = lane; e < np; e += 64) zr[e] -= fct * prow[wM + e];
     }
     __syncthreads();
   }
   // x_j = Z[ordv[j]] / pivot_j, rows scaled by rs
   for (int e = tid; e < np * np; e += NT) {
-    int j = e / np, col = e - j * np;
+    const int j = e / np, col = e - j * np;
     double v = 0.0;
     if (j < n) {
-      v = Z[c.ordv[j] * np + col] / c.dtmp[j];
+      v = Z[(size_t)c.ordv[j] * np + col] / c.dtmp[j];
       if (rs) v *= rs[j];
     }
     dst[e] = v;
@@ -597,7 +745,7 @@ __device__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double* Z, double* dst,
 // The result replaces c.G[spin] (and G64 when g64 != null); returns the drift
 // max|G_old - G_new| and writes log|det| into *logdet.
 template <typename WT>
-__device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const double* dL,
+__device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const double* dL,
                               const double* TL, const double* UR, const double* dR,
                               const double* TR, double* g64, double* logdet, bool drift) {
   const int np = c.np, n = c.n, tid = threadIdx.x;
@@ -612,7 +760,7 @@ __device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const doub
   }
   __syncthreads();
   // M = DLb^{-1} (UL^T UR) DRb^{-1};  Z = DLb^{-1} UL^T
-  wg_gemm<double>(1, np, np, np, UL, UL, 1, np, UR, UR, np, 1,
+  ctx_gemm<double>(c, 1, np, np, np, UL, UL, 1, np, UR, UR, np, 1,
                   [&](int, int i, int j, double v) { M[i * np + j] = v * iLb[i] * iRb[j]; });
   for (int e = tid; e < np * np; e += NT) {
     int i = e / np, j = e - i * np;
@@ -620,7 +768,7 @@ __device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const doub
   }
   __syncthreads();
   // M += DLs (TL TR^T) DRs
-  wg_gemm<double>(1, np, np, np, TL, TL, np, 1, TR, TR, 1, np, [&](int, int i, int j, double v) {
+  ctx_gemm<double>(c, 1, np, np, np, TL, TL, np, 1, TR, TR, 1, np, [&](int, int i, int j, double v) {
     M[i * np + j] += fmin(dL[i], 1.0) * v * fmin(dR[j], 1.0);
   });
   __syncthreads();
@@ -630,7 +778,7 @@ __device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const doub
   WT* G = c.G[spin];
   double dmax = 0.0;
   bool bad = false;
-  wg_gemm<double>(1, np, np, np, UR, UR, np, 1, M, M, np, 1, [&](int, int i, int j, double v) {
+  ctx_gemm<double>(c, 1, np, np, np, UR, UR, np, 1, M, M, np, 1, [&](int, int i, int j, double v) {
     const int e = i * np + j;
     if (drift) dmax = fmax(dmax, fabs((double)G[e] - v));
     if (!(fabs(v) < 1e300)) bad = true;
@@ -658,7 +806,7 @@ __device__ double fresh_green(Ctx<WT>& c, int spin, const double* UL, const doub
 // G^sigma(l) = B_l G^sigma(l-1) B_l^{-1} = V_l expK G expKinv V_l^{-1} for both spins:
 // two MFMA products per spin in the working precision, the diagonal factors in the epilogue.
 template <typename WT>
-__device__ void wrap_both(Ctx<WT>& c, int l) {
+__device__ __forceinline__ void wrap_both(Ctx<WT>& c, int l) {
   const KArgs& a = *c.a;
   const int np = c.np;
   slice_scales(c, l - 1);
@@ -666,10 +814,10 @@ __device__ void wrap_both(Ctx<WT>& c, int l) {
   WT* t1 = (WT*)c.w2;
   const WT* K1 = kexp<WT>(a);
   const WT* K2 = kexpinv<WT>(a);
-  wg_gemm<WT>(2, np, np, np, K1, K1, np, 1, c.G[0], c.G[1], np, 1,
+  ctx_gemm<WT>(c, 2, np, np, np, K1, K1, np, 1, c.G[0], c.G[1], np, 1,
               [&](int b, int i, int j, WT v) { (b ? t1 : t0)[i * np + j] = v; });
   __syncthreads();
-  wg_gemm<WT>(2, np, np, np, t0, t1, np, 1, K2, K2, np, 1, [&](int b, int i, int j, WT v) {
+  ctx_gemm<WT>(c, 2, np, np, np, t0, t1, np, 1, K2, K2, np, 1, [&](int b, int i, int j, WT v) {
     c.G[b][i * np + j] = (WT)(c.sr[b * np + i] * (double)v * c.sc[b * np + j]);
   });
   __syncthreads();
@@ -691,7 +839,7 @@ __device__ void wrap_both(Ctx<WT>& c, int l) {
 //     Y[m,c] = delta_{c,j_m} - G0[j_m, c] - sum_{m'<m} X[j_m, m'] Y[m', c]
 // and the rank-m correction applied as one MFMA product.
 template <typename WT>
-__device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
+__device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
   const KArgs& a = *c.a;
   const int n = c.n, np = c.np, K = c.K, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int K2 = K * K;
@@ -819,7 +967,7 @@ __device__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
       WT* Y0 = c.xy + (size_t)np * K;
       WT* X1 = c.xy + 2 * (size_t)np * K;
       WT* Y1 = c.xy + 3 * (size_t)np * K;
-      wg_gemm<WT>(2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1,
+      ctx_gemm<WT>(c, 2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1,
                   [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
     }
     __syncthreads();
@@ -854,7 +1002,7 @@ __device__ __forceinline__ double* lftD(Ctx<WT>& c, int sp) { return lftU(c, sp)
 
 // Build stack entries j = J-1 down to j_lo: entry j = UDT of B(L, j*stab)^T.
 template <typename WT>
-__device__ void build_right(Ctx<WT>& c, int j_lo) {
+__device__ __forceinline__ void build_right(Ctx<WT>& c, int j_lo) {
   const KArgs& a = *c.a;
   for (int sp = 0; sp < 2; ++sp) {
     for (int j = c.J - 1; j >= j_lo; --j) {
@@ -868,7 +1016,7 @@ __device__ void build_right(Ctx<WT>& c, int j_lo) {
 
 // Load the working G from the FP64 record.
 template <typename WT>
-__device__ void load_green(Ctx<WT>& c) {
+__device__ __forceinline__ void load_green(Ctx<WT>& c) {
   const size_t nn = (size_t)c.np * c.np;
   for (size_t e = threadIdx.x; e < 2 * nn; e += NT) {
     int sp = (int)(e / nn);
@@ -879,7 +1027,7 @@ __device__ void load_green(Ctx<WT>& c) {
 
 // ------------------------------------------------------------------------------ operations
 template <typename WT>
-__device__ void op_init(Ctx<WT>& c, int idx) {
+__device__ __forceinline__ void op_init(Ctx<WT>& c, int idx) {
   const KArgs& a = *c.a;
   const int n = c.n, np = c.np, L = c.L, tid = threadIdx.x;
   // fields: drawn from the seed or copied and validated
@@ -912,7 +1060,7 @@ __device__ void op_init(Ctx<WT>& c, int idx) {
 }
 
 template <typename WT>
-__device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
+__device__ __forceinline__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
   const KArgs& a = *c.a;
   const int np = c.np, L = c.L, tid = threadIdx.x;
   load_green(c);
@@ -975,7 +1123,7 @@ __device__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
 // Fresh G(slice) of the current field from scratch (left chain from slice 1, right chain from
 // slice L, both chunked by stab), into the working G of both spins.
 template <typename WT>
-__device__ void fresh_at(Ctx<WT>& c, int slice) {
+__device__ __forceinline__ void fresh_at(Ctx<WT>& c, int slice) {
   const KArgs& a = *c.a;
   const int L = c.L;
   for (int sp = 0; sp < 2; ++sp) {
@@ -1008,7 +1156,7 @@ __device__ void fresh_at(Ctx<WT>& c, int slice) {
 }
 
 template <typename WT>
-__device__ void op_debug_green(Ctx<WT>& c, int chain) {
+__device__ __forceinline__ void op_debug_green(Ctx<WT>& c, int chain) {
   const KArgs& a = *c.a;
   const int n = c.n, np = c.np;
   fresh_at(c, a.slice);
@@ -1021,7 +1169,7 @@ __device__ void op_debug_green(Ctx<WT>& c, int chain) {
 }
 
 template <typename WT>
-__device__ void op_debug_ratios(Ctx<WT>& c, int chain) {
+__device__ __forceinline__ void op_debug_ratios(Ctx<WT>& c, int chain) {
   const KArgs& a = *c.a;
   const int n = c.n, np = c.np;
   fresh_at(c, a.slice);
