@@ -128,6 +128,77 @@ def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh
                 phase_share=share)
 
 
+def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick: int,
+                refresh: int, seed: int = 4):
+    """Continuous batching of a Poisson stream of chain requests (lattice L x L, beta, sweep
+    count drawn as in the serving workload), warm pools for every model of the mix."""
+    from paper_2106_00712_amd.serving import GpuExecutor, Request, Server, latency_stats
+    reqs = [r for r in di.serving_requests(4 * n_req, rate, seed) if r["L"] in Ls][:n_req]
+    ex = GpuExecutor(di.square_hopping, U=4.0, dtau=0.1, stab_every=10,
+                     refresh_every=refresh if precision == "fp32_wrap" else 0)
+    srv = Server(ex, hbm_budget=64 << 30, tick_sweeps=tick, pool_capacity=capacity,
+                 precision=precision)
+    srv.warm([(L, b) for L in Ls for b in di.SERVING_BETA])
+    # the arrival times are re-based so that the first request arrives at t = 0
+    t_first = reqs[0]["arrival"]
+    rq = [Request(d["id"], d["L"], d["beta"], d["sweeps"], d["seed"], d["arrival"] - t_first)
+          for d in reqs]
+    t0 = time.perf_counter()
+    res = srv.run(rq)
+    wall = time.perf_counter() - t0
+    st = latency_stats(res)
+    span = rq[-1].arrival if len(rq) > 1 else 0.0
+    return {"rate_req_per_s": rate, "offered_rate_req_per_s": (len(rq) - 1) / span if span > 0 else None,
+            "requests": len(res), "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+            "mean_s": st["mean_s"], "updates_per_s": srv.updates / wall, "wall_s": wall,
+            "ticks": srv.ticks, "precision": precision, "lattices_L": list(Ls),
+            "pool_capacity": capacity, "tick_sweeps": tick}
+
+
+def run_mixed(steps: int, refresh: int, n_each: int):
+    """Honeycomb 6x6 (N = 72) and 12x12 (N = 288) chains side by side in one recorded graph,
+    FP32 wraps with FP64 refresh every `refresh` slices, against the same batches in FP64."""
+    import torch
+    from paper_2106_00712_amd import dqmc
+    ws = [di.WORKLOADS["honeycomb6x6_U3_b6"], di.WORKLOADS["honeycomb12x12_U3_b6"]]
+    out = {"workload": "honeycomb 6x6 + 12x12, U=3, beta=6", "chains_each": n_each, "steps": steps}
+    for prec in ("fp64", "fp32_wrap"):
+        bs = []
+        for w in ws:
+            m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, precision=prec,
+                                refresh_every=refresh if prec == "fp32_wrap" else 0)
+            bs.append(dqmc.Batch(m, w.seeds(n_each), w.fields(n_each)))
+        g = dqmc.Graph(bs, [1, 1])
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ups = sum(n_each * w.n_slices * w.n_sites for w in ws) * steps
+        obs = [b.measure() for b in bs]
+        out[prec] = {"updates_per_s": ups / wall, "ms_per_step": wall * 1e3 / steps,
+                     "max_abs_dG_at_refresh": [float(o["max_drift"].max()) for o in obs],
+                     "double_occ": [float(o["double_occ"].mean()) for o in obs],
+                     "flags": [int(np.bitwise_or.reduce(o["flags"])) for o in obs]}
+        g.close()
+        for b in bs:
+            b.close()
+    out["fp32_wrap"]["speedup_vs_fp64"] = out["fp32_wrap"]["updates_per_s"] / out["fp64"]["updates_per_s"]
+    out["fp32_wrap"]["fixed_field_wrap_error"] = [fp32_wrap_error(w, 2, 1e-5) for w in ws]
+    return out
+
+
+def fp32_wrap_error(w, n_chains: int, bound: float):
+    """FP32-wrap error on fixed fields against the FP64 fresh G, per refresh interval."""
+    from paper_2106_00712_amd.autotune import Autotuner
+    return Autotuner().refresh_interval(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(n_chains),
+                                        w.seeds(n_chains), bound=bound,
+                                        candidates=(2, 3, 4, 5, 6, 8, 10),
+                                        stab_every=w.stab_every)
+
+
 def cpu_baseline(w, n_chains: int, n_sweeps: int):
     """The CPU oracle, as it is, on a bounded sample of the same workload."""
     from oracle import Model, OracleChains
@@ -151,11 +222,22 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--delay-rank", type=int, default=0)
-    ap.add_argument("--refresh", type=int, default=4, help="FP32-wrap FP64 refresh interval")
+    ap.add_argument("--refresh", type=int, default=0,
+                    help="FP32-wrap FP64 refresh interval (0: the longest within max|dG| <= 1e-5 "
+                         "on fixed fields, chosen by the autotuner)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=12)
     ap.add_argument("--cpu-sweeps", type=int, default=8)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="only the serving workload over every lattice size (minutes per rate)")
+    ap.add_argument("--workload", default=None,
+                    help="only a throughput line for this workload (e.g. square20x20_U8_b10)")
+    ap.add_argument("--chains", type=int, default=0, help="with --workload: number of chains")
+    ap.add_argument("--precision", default="fp64", help="with --workload: fp64 or fp32_wrap")
+    ap.add_argument("--mixed", action="store_true",
+                    help="only the mixed-size batch: honeycomb 6x6 + 12x12, FP32 wraps, one graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -163,6 +245,38 @@ def main():
         print("bench.py measures one GPU: chains are independent, so a multi-GPU run is the "
               "one-GPU run per device; this build launches on one GPU only.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload:
+        wl = di.WORKLOADS[args.workload]
+        if args.chains:
+            wl = di.Workload(wl.name, wl.config_id, wl.lattice, wl.L, wl.U, wl.beta, wl.dtau,
+                             args.chains, wl.n_sweeps, wl.stab_every)
+        r = run_gpu(wl, args.precision, args.steps, args.warmup, args.delay_rank,
+                    (args.refresh or 10) if args.precision == "fp32_wrap" else 0)
+        o = r["obs"]
+        ups = wl.n_chains * wl.n_slices * wl.n_sites
+        acc = float(o["accepted"].sum() / max(1, o["attempted"].sum()))
+        flw = algorithmic_flops(wl.n_sites, wl.n_slices, r["batch"].stab, acc)
+        tl = float(np.mean(r["per_launch_ms"])) * 1e-3
+        print(json.dumps({"workload": wl.name, "precision": args.precision, "n_chains": wl.n_chains,
+                          "n_sites": wl.n_sites, "n_slices": wl.n_slices, "steps": args.steps,
+                          "ms_per_sweep": tl * 1e3, "updates_per_s": ups / tl,
+                          "tflops": flw["total"] * wl.n_chains / tl / 1e12,
+                          "frac_fp64_peak": flw["total"] * wl.n_chains / tl / PEAK_FP64_MFMA,
+                          "kernel_variant": r["batch"].variant, "delay_rank": r["batch"].delay_rank,
+                          "stab": r["batch"].stab, "init_ms": r["init_ms"],
+                          "max_drift": float(o["max_drift"].max()),
+                          "double_occ": float(o["double_occ"].mean()),
+                          "flags": int(np.bitwise_or.reduce(o["flags"])),
+                          "phase_share": r["phase_share"]}))
+        return
+    if args.mixed:
+        print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256)))
+        return
+    if args.serving_full:
+        out = [run_serving(rate, 48, di.SERVING_L, "fp64", 16, 10, 0) for rate in (50, 2000)]
+        print(json.dumps({"serving_full": out}))
+        return
 
     if args.copy_calibration:
         import torch
@@ -212,17 +326,28 @@ def main():
         "flags": int(np.bitwise_or.reduce(o["flags"])),
     }
     if not args.no_fp32:
-        r32 = run_gpu(w, "fp32_wrap", args.steps, args.warmup, args.delay_rank, args.refresh)
+        werr = fp32_wrap_error(w, 4, 1e-5)
+        refresh = args.refresh or werr["refresh_every"]
+        r32 = run_gpu(w, "fp32_wrap", args.steps, args.warmup, args.delay_rank, refresh)
         o32 = r32["obs"]
         v32 = upd_step * args.steps / r32["wall"]
-        line["fp32_wrap"] = {"value": v32, "unit": "updates/s", "refresh_every": args.refresh,
+        line["fp32_wrap"] = {"value": v32, "unit": "updates/s", "refresh_every": refresh,
                              "ms_per_step": r32["wall"] * 1e3 / args.steps,
-                             "max_abs_dG_vs_fp64": float(o32["max_drift"].max()),
+                             "max_abs_dG_fixed_fields": werr["max_abs_dG"].get(str(refresh)),
+                             "fixed_field_wrap_error": werr,
+                             "max_abs_dG_at_refresh_in_sweeps": float(o32["max_drift"].max()),
                              "speedup_vs_fp64": v32 / value,
                              "phase_share": r32["phase_share"],
                              "double_occ": float(o32["double_occ"].mean()),
                              "double_occ_fp64": float(o["double_occ"].mean()),
                              "flags": int(np.bitwise_or.reduce(o32["flags"]))}
+    if not args.no_serving:
+        fast_L = tuple(L for L in di.SERVING_L if L * L <= 64)
+        line["serving"] = {
+            "note": "Poisson stream of the serving workload restricted to the lattices of the "
+                    "N <= 64 kernels (L in 4, 6, 8); warm pools, continuous batching",
+            "fp64": [run_serving(rate, 48, fast_L, "fp64", 16, 10, 0) for rate in (100, 1000)],
+        }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_chains, args.cpu_sweeps)
     print(json.dumps(line))

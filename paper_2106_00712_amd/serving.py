@@ -8,13 +8,15 @@ server
 
   1. admits waiting requests into free slots of their model's pool (dqmc_init_slots), creating
      the pool first if the HBM budget (sum over pools of capacity x dqmc_chain_bytes) allows;
-  2. launches one persistent kernel per non-idle pool (dqmc_sweep_counts), each on its own
-     stream so that pools of different lattices run side by side on the device, every occupied
-     slot advancing by min(tick_sweeps, remaining sweeps);
-  3. measures the pools whose chains finished and frees those slots.
+  2. launches one persistent kernel (dqmc_sweep_counts) on every idle pool with occupied slots,
+     each pool on its own stream so that pools of different lattices run side by side on the
+     device, every occupied slot advancing by min(tick_sweeps, remaining sweeps);
+  3. polls the running pools; a pool whose launch has finished is measured, its finished
+     requests leave and their slots free up, and it becomes idle again.
 
-A request that arrives while others are on the GPU therefore starts at the next tick, in a slot
-freed by a finished one.  Each chain's trajectory is a function of its seed and field alone
+Pools tick independently: a short request is never held back by a slow pool.  A request that
+arrives while others are on the GPU starts at the next tick of its pool, in a free slot or a
+slot freed by a finished one.  Each chain's trajectory is a function of its seed and field alone
 (counter-based random numbers, one workgroup per chain), so its result does not depend on the
 pool, the slot or the other requests.
 
@@ -70,6 +72,7 @@ class _Pool:
     capacity: int
     handle: object                       # executor's pool object
     slots: Dict[int, _Slot] = field(default_factory=dict)
+    running: Optional[np.ndarray] = None  # sweep counts of the launch in flight
 
     def free_slots(self) -> List[int]:
         return [i for i in range(self.capacity) if i not in self.slots]
@@ -96,6 +99,11 @@ class Server:
 
     def _key(self, r: Request) -> ModelKey:
         return (r.L, float(r.beta), self.precision)
+
+    def warm(self, models: Sequence[Tuple[int, float]]):
+        """Create the pools of the given (L, beta) models ahead of traffic (a warm server)."""
+        for L, beta in models:
+            self._pool_for((int(L), float(beta), self.precision))
 
     def submit(self, r: Request):
         if r.sweeps < 1:
@@ -136,7 +144,7 @@ class Server:
         for r in self.queue:
             key = self._key(r)
             pool = self._pool_for(key)
-            free = pool.free_slots() if pool is not None else []
+            free = pool.free_slots() if (pool is not None and pool.running is None) else []
             if not free:
                 waiting.append(r)
                 continue
@@ -146,37 +154,50 @@ class Server:
             self.ex.init_slots(self.pools[key].handle, [s for s, _ in items], [r for _, r in items])
         self.queue = waiting
 
-    def step(self, now_fn: Callable[[], float]) -> List[Result]:
-        """Admit, run one tick, retire; returns the requests finished in this tick."""
-        self._admit(now_fn())
-        work = []
-        for key, pool in self.pools.items():
-            if not pool.slots:
-                continue
-            counts = np.zeros(pool.capacity, dtype=np.int32)
-            for s, sl in pool.slots.items():
-                counts[s] = min(self.tick_sweeps, sl.remaining)
-            work.append((pool, counts))
-        if not work:
-            return []
-        self.ex.run_tick([(p.handle, c) for p, c in work])
-        self.ticks += 1
+    def _launch_idle(self):
+        for pool in self.pools.values():
+            if pool.running is None and pool.slots:
+                counts = np.zeros(pool.capacity, dtype=np.int32)
+                for s, sl in pool.slots.items():
+                    counts[s] = min(self.tick_sweeps, sl.remaining)
+                self.ex.launch_tick(pool.handle, counts)
+                pool.running = counts
+                self.ticks += 1
+
+    def _retire(self, pool: _Pool, now_fn: Callable[[], float]) -> List[Result]:
+        counts, pool.running = pool.running, None
+        finished = []
+        for s, sl in pool.slots.items():
+            sl.remaining -= int(counts[s])
+            self.updates += int(counts[s]) * pool.key[0] ** 2 * self.ex.n_slices(pool.key)
+            if sl.remaining == 0:
+                finished.append(s)
         done: List[Result] = []
-        for pool, counts in work:
-            finished = []
-            for s, sl in pool.slots.items():
-                sl.remaining -= int(counts[s])
-                self.updates += int(counts[s]) * pool.key[0] ** 2 * self.ex.n_slices(pool.key)
-                if sl.remaining == 0:
-                    finished.append(s)
-            if finished:
-                obs, fields = self.ex.measure(pool.handle, finished, self.keep_fields)
-                t = now_fn()
-                for j, s in enumerate(finished):
-                    sl = pool.slots.pop(s)
-                    done.append(Result(sl.req.rid, obs[j], sl.req.arrival, sl.admitted, t,
-                                       fields[j] if fields is not None else None))
+        if finished:
+            obs, fields = self.ex.measure(pool.handle, finished, self.keep_fields)
+            t = now_fn()
+            for j, s in enumerate(finished):
+                sl = pool.slots.pop(s)
+                done.append(Result(sl.req.rid, obs[j], sl.req.arrival, sl.admitted, t,
+                                   fields[j] if fields is not None else None))
         return done
+
+    def step(self, now_fn: Callable[[], float], wait_until: Optional[float] = None) -> List[Result]:
+        """Admit into idle pools, launch every idle pool with work, then retire the pools whose
+        launch has finished (waiting for the first to finish, or until wait_until)."""
+        self._admit(now_fn())
+        self._launch_idle()
+        running = [p for p in self.pools.values() if p.running is not None]
+        if not running:
+            return []
+        ready = [p for p in running if self.ex.done(p.handle)]
+        if not ready:
+            self.ex.wait_any([p.handle for p in running], wait_until, now_fn)
+            ready = [p for p in running if self.ex.done(p.handle)]
+        out: List[Result] = []
+        for p in ready:
+            out.extend(self._retire(p, now_fn))
+        return out
 
     def run(self, requests: Sequence[Request], clock: Optional[Callable[[], float]] = None,
             realtime: bool = True) -> List[Result]:
@@ -191,14 +212,15 @@ class Server:
             while i < len(arrivals) and (not realtime or arrivals[i].arrival <= t):
                 self.submit(arrivals[i])
                 i += 1
+            nxt = arrivals[i].arrival if (realtime and i < len(arrivals)) else None
             if not self.pending():
-                dt = arrivals[i].arrival - t      # idle: wait for the next arrival
+                dt = nxt - t                      # idle: wait for the next arrival
                 if clock is None:
                     time.sleep(max(dt, 0.0))
                 else:
                     self.ex.advance(max(dt, 0.0))
                 continue
-            results.extend(self.step(now))
+            results.extend(self.step(now, wait_until=nxt))
         return results
 
 
@@ -263,18 +285,23 @@ class GpuExecutor:
         with torch.cuda.stream(pool["stream"]):
             b.init_slots(slots, seeds, fields, stream=pool["stream"])
 
-    def run_tick(self, work):
+    def launch_tick(self, pool, counts):
         torch = self.torch
-        cur = torch.cuda.current_stream(self.device)
-        for pool, counts in work:
-            s = pool["stream"]
-            s.wait_stream(cur)
-            with torch.cuda.stream(s):
-                pool["counts"].copy_(torch.from_numpy(counts), non_blocking=False)
-                pool["batch"].sweep_counts(pool["counts"], stream=s)
-                pool["done"].record(s)
-        for pool, _ in work:
-            pool["done"].synchronize()
+        s = pool["stream"]
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            pool["counts"].copy_(torch.from_numpy(counts), non_blocking=False)
+            pool["batch"].sweep_counts(pool["counts"], stream=s)
+            pool["done"].record(s)
+
+    def done(self, pool) -> bool:
+        return bool(pool["done"].query())
+
+    def wait_any(self, pools, until, now_fn):
+        while not any(p["done"].query() for p in pools):
+            if until is not None and now_fn() >= until:
+                return
+            time.sleep(2e-4)
 
     def measure(self, pool, slots, keep_fields):
         b = pool["batch"]

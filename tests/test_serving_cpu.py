@@ -40,15 +40,25 @@ class SimExecutor:
             p["slot"][s] = {"rid": r.rid, "seed": r.seed, "done": 0}
             self.events.append(("admit", r.rid, self.clock))
 
-    def run_tick(self, work):
-        cost = 0.0
-        for p, counts in work:
-            assert counts.shape == (p["cap"],)
-            for s, c in enumerate(counts):
-                if c:
-                    p["slot"][s]["done"] += int(c)
-            cost = max(cost, counts.max() * p["key"][0] ** 2 * p["key"][1] * 1e-6)
-        self.clock += cost
+    def launch_tick(self, p, counts):
+        assert counts.shape == (p["cap"],) and "busy_until" not in p
+        for s, c in enumerate(counts):
+            if c:
+                p["slot"][s]["done"] += int(c)
+        p["busy_until"] = self.clock + counts.max() * p["key"][0] ** 2 * p["key"][1] * 1e-6
+        self.events.append(("launch", p["key"], self.clock))
+
+    def done(self, p):
+        if "busy_until" in p and self.clock >= p["busy_until"]:
+            del p["busy_until"]
+            return True
+        return False
+
+    def wait_any(self, pools, until, now_fn):
+        t = min(p["busy_until"] for p in pools)
+        if until is not None:
+            t = min(t, until)
+        self.clock = max(self.clock, t)
 
     def measure(self, p, slots, keep_fields):
         out = np.zeros(len(slots), dtype=OBS_DTYPE)
@@ -112,6 +122,17 @@ def test_results_do_not_depend_on_the_mix():
         _, _, res = _serve([alone], hbm_budget=10 ** 9, tick_sweeps=3, pool_capacity=1)
         m = [r for r in mixed if r.rid == q.rid][0]
         assert res[0].obs.tobytes() == m.obs.tobytes()
+
+
+def test_pools_tick_independently():
+    # a long L = 16 request must not hold back a stream of short L = 4 requests
+    reqs = [Request(0, 16, 8.0, 100, 1, 0.0)] + [Request(k, 4, 2.0, 10, 100 + k, 1e-3 * k)
+                                                 for k in range(1, 9)]
+    ex, srv, res = _serve(reqs, hbm_budget=10 ** 9, tick_sweeps=10, pool_capacity=4)
+    by = {r.rid: r for r in res}
+    short = max(by[k].finished for k in range(1, 9))
+    assert short < by[0].finished
+    assert all(by[k].latency < 0.5 * by[0].latency for k in range(1, 9))
 
 
 def test_latency_stats():
