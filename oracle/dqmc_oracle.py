@@ -186,6 +186,27 @@ def measure_from_green(T: np.ndarray, G_up: np.ndarray, G_dn: np.ndarray):
     return docc, dens, kin / N
 
 
+def spin_structure(G_up: np.ndarray, G_dn: np.ndarray, eps: np.ndarray) -> float:
+    """Staggered spin structure factor (1/N) sum_ij eps_i eps_j <s^z_i s^z_j> for one field, with
+    s^z_i = (n_i,up - n_i,dn)/2 and a form factor eps_i = +-1 (the structure factor S(Q) of the
+    paper's loss function at a wave vector whose phases are eps_i; eps = 1 gives S(Gamma) without
+    a sublattice sign).
+
+    Wick's theorem at fixed field, spins independent:
+      <n_i,s n_j,s'> = (1 - G^s_ii)(1 - G^s'_jj) + delta_ss' (delta_ij - G^s_ji) G^s_ij,
+    so with m = sum_i eps_i (G^dn_ii - G^up_ii)
+      (1/N) sum_ij eps_i eps_j <s^z_i s^z_j>
+        = (1/(4N)) [ m^2 + sum_s ( sum_i G^s_ii - sum_ij eps_i eps_j G^s_ij G^s_ji ) ].
+    """
+    N = G_up.shape[0]
+    e = np.asarray(eps, dtype=np.float64)
+    m = float(np.sum(e * (np.diag(G_dn) - np.diag(G_up))))
+    tot = m * m
+    for G in (G_up, G_dn):
+        tot += float(np.trace(G)) - float(np.sum(np.outer(e, e) * G * G.T))
+    return tot / (4.0 * N)
+
+
 # -------------------------------------------------------------------------------- chains
 @dataclass
 class ChainState:
@@ -288,12 +309,14 @@ class OracleChains:
             for _ in range(n_sweeps):
                 self._sweep_chain(self.chains[c])
 
-    def measure(self):
-        """Per-chain observables from G(0) after the last sweep (one dict per chain)."""
+    def measure(self, stagger=None):
+        """Per-chain observables from G(0) after the last sweep (one dict per chain); with a form
+        factor `stagger` (+-1 per site) also the staggered spin structure factor."""
         out = []
         for st in self.chains:
             docc, dens, kin = measure_from_green(self.m.T, st.G[0], st.G[1])
-            out.append(dict(double_occ=docc, density=dens, kinetic=kin,
+            saf = spin_structure(st.G[0], st.G[1], stagger) if stagger is not None else None
+            out.append(dict(double_occ=docc, density=dens, kinetic=kin, spin_af=saf,
                             logdet_up=st.logdet[0], logdet_dn=st.logdet[1],
                             max_drift=st.max_drift, max_logdet_err=st.max_logdet_err,
                             attempted=st.attempted, accepted=st.accepted,

@@ -324,3 +324,49 @@ def test_chain_statistics_match_enumeration():
     for k, exact in enumerate((Dx, Ex)):
         mu, se = means[:, k].mean(), means[:, k].std(ddof=1) / math.sqrt(n_chains)
         assert abs(mu - exact) < 4 * se + 1e-12, (k, mu, se, exact)
+
+
+# ------------------------------------------------------------------ spin structure factor
+def _fock_spin_structure(T, U, dtau, n_slices, eps):
+    """(1/N) <(sum_i eps_i s^z_i)^2> in the Trotterised Fock space (exact for the discrete model)."""
+    N = T.shape[0]
+    c = ex.fock_operators(2 * N)
+    cd = [op.T for op in c]
+    n = [cd[m] @ c[m] for m in range(2 * N)]
+    dim = c[0].shape[0]
+    I = np.eye(dim)
+    Hk = sum(T[i, j] * cd[s * N + i] @ c[s * N + j]
+             for s in range(2) for i in range(N) for j in range(N) if T[i, j] != 0.0)
+    Hu = sum(U * (n[i] - 0.5 * I) @ (n[N + i] - 0.5 * I) for i in range(N))
+    import scipy.linalg as sla
+    P = np.linalg.matrix_power(np.diag(np.exp(-dtau * np.diag(Hu))) @ sla.expm(-dtau * Hk), n_slices)
+    Mz = sum(eps[i] * 0.5 * (n[i] - n[N + i]) for i in range(N))
+    return float(np.trace(P @ Mz @ Mz) / np.trace(P)) / N
+
+
+@pytest.mark.parametrize("stag", [True, False])
+def test_spin_structure_equals_fock_trace(stag):
+    """The Wick estimator averaged over all HS fields of a 2x2 lattice equals the Fock-space trace
+    of (1/N)(sum eps s^z)^2, staggered (eps = (-1)^(x+y)) and uniform (eps = 1)."""
+    from oracle import spin_structure
+    T = di.square_hopping(2)
+    eps = di.staggered_sign("square", 2) if stag else np.ones(4)
+    U, dtau, Lt = 4.0, 0.1, 3
+    fields, w, Gu, Gd = ex.enumerate_fields(T, U, dtau, Lt)
+    vals = np.array([spin_structure(Gu[k], Gd[k], eps) for k in range(fields.shape[0])])
+    hs = float(np.sum(w * vals) / np.sum(w))
+    fock = _fock_spin_structure(T, U, dtau, Lt, eps)
+    assert math.isclose(hs, fock, rel_tol=1e-11), (hs, fock)
+
+
+def test_spin_structure_free_fermions():
+    """U = 0: G^up = G^dn = G free, so m = 0 and S = (1/(4N)) 2 (tr G - sum eps eps G_ij G_ji);
+    on the 4x4 lattice at beta = 2 the uniform S(Gamma) equals the free-fermion value of
+    (1/N)<(S^z)^2> = (1/(2N)) sum_k f_k (1 - f_k) (one-body modes, both spins)."""
+    from oracle import spin_structure
+    T = di.square_hopping(4)
+    G = ex.free_green(T, 2.0)
+    lam = np.linalg.eigvalsh(T)
+    f = 1.0 / (1.0 + np.exp(2.0 * lam))
+    ref = float(np.sum(f * (1 - f))) / (2 * 16)
+    assert math.isclose(spin_structure(G, G, np.ones(16)), ref, rel_tol=1e-12)
