@@ -186,24 +186,25 @@ def measure_from_green(T: np.ndarray, G_up: np.ndarray, G_dn: np.ndarray):
     return docc, dens, kin / N
 
 
-def spin_structure(G_up: np.ndarray, G_dn: np.ndarray, eps: np.ndarray) -> float:
-    """Staggered spin structure factor (1/N) sum_ij eps_i eps_j <s^z_i s^z_j> for one field, with
-    s^z_i = (n_i,up - n_i,dn)/2 and a form factor eps_i = +-1 (the structure factor S(Q) of the
-    paper's loss function at a wave vector whose phases are eps_i; eps = 1 gives S(Gamma) without
-    a sublattice sign).
+def spin_structure(G_up: np.ndarray, G_dn: np.ndarray, form: np.ndarray) -> float:
+    """(1/N) sum_ij f_i f_j <s^z_i s^z_j> for one field, s^z_i = (n_i,up - n_i,dn)/2, with a real
+    form factor f (the magnetic structure factor S(Q) of the paper's loss function, main text
+    eq. (4): with phases f_i = +-1 it is S(Q) at a wave vector whose phases are real, e.g. the
+    sublattice sign for honeycomb S(Gamma); a complex phase e^{iQ.r} splits into f = cos and
+    f = sin, and S(Q) is the sum of the two).
 
     Wick's theorem at fixed field, spins independent:
       <n_i,s n_j,s'> = (1 - G^s_ii)(1 - G^s'_jj) + delta_ss' (delta_ij - G^s_ji) G^s_ij,
-    so with m = sum_i eps_i (G^dn_ii - G^up_ii)
-      (1/N) sum_ij eps_i eps_j <s^z_i s^z_j>
-        = (1/(4N)) [ m^2 + sum_s ( sum_i G^s_ii - sum_ij eps_i eps_j G^s_ij G^s_ji ) ].
+    so with m = sum_i f_i (G^dn_ii - G^up_ii)
+      (1/N) sum_ij f_i f_j <s^z_i s^z_j>
+        = (1/(4N)) [ m^2 + sum_s ( sum_i f_i^2 G^s_ii - sum_ij f_i f_j G^s_ij G^s_ji ) ].
     """
     N = G_up.shape[0]
-    e = np.asarray(eps, dtype=np.float64)
-    m = float(np.sum(e * (np.diag(G_dn) - np.diag(G_up))))
+    f = np.asarray(form, dtype=np.float64)
+    m = float(np.sum(f * (np.diag(G_dn) - np.diag(G_up))))
     tot = m * m
     for G in (G_up, G_dn):
-        tot += float(np.trace(G)) - float(np.sum(np.outer(e, e) * G * G.T))
+        tot += float(np.sum(f * f * np.diag(G))) - float(np.sum(np.outer(f, f) * G * G.T))
     return tot / (4.0 * N)
 
 

@@ -344,13 +344,15 @@ def _fock_spin_structure(T, U, dtau, n_slices, eps):
     return float(np.trace(P @ Mz @ Mz) / np.trace(P)) / N
 
 
-@pytest.mark.parametrize("stag", [True, False])
-def test_spin_structure_equals_fock_trace(stag):
+@pytest.mark.parametrize("form", ["staggered", "uniform", "random"])
+def test_spin_structure_equals_fock_trace(form):
     """The Wick estimator averaged over all HS fields of a 2x2 lattice equals the Fock-space trace
-    of (1/N)(sum eps s^z)^2, staggered (eps = (-1)^(x+y)) and uniform (eps = 1)."""
+    of (1/N)(sum f s^z)^2: staggered f = (-1)^(x+y), uniform f = 1, and a random real f (which
+    tells the f^2 weight of the diagonal term from a plain trace)."""
     from oracle import spin_structure
     T = di.square_hopping(2)
-    eps = di.staggered_sign("square", 2) if stag else np.ones(4)
+    eps = {"staggered": di.staggered_sign("square", 2), "uniform": np.ones(4),
+           "random": np.random.default_rng(5).uniform(-1.5, 1.5, 4)}[form]
     U, dtau, Lt = 4.0, 0.1, 3
     fields, w, Gu, Gd = ex.enumerate_fields(T, U, dtau, Lt)
     vals = np.array([spin_structure(Gu[k], Gd[k], eps) for k in range(fields.shape[0])])
