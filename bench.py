@@ -190,6 +190,66 @@ def run_mixed(steps: int, refresh: int, n_each: int):
     return out
 
 
+# Good-DQMC column of the paper's Table 2 (honeycomb, L = 6, U = 3.83, beta = 6, dtau = 0.1)
+PAPER_TABLE2 = {"E_k": (-1.358, 0.001), "S_Gamma": (3.00, 0.04)}
+
+
+def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
+    """Thermalised chains at the paper's honeycomb point; E_k and the sublattice-signed S(Gamma)
+    per chain (time average over `meas` sweeps, one measurement at G(0) after each sweep), then
+    the mean and standard error over the independent chains."""
+    import torch
+    from paper_2106_00712_amd import dqmc
+    w = di.WORKLOADS["honeycomb6x6_U3.83_b6"]
+    eps = di.staggered_sign(w.lattice, w.L)
+    m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    b = dqmc.Batch(m, w.seeds(n_chains, seed_first))
+    t0 = time.perf_counter()
+    for k in range(therm):
+        b.sweep(1)
+        if (k + 1) % 50 == 0:
+            torch.cuda.synchronize()
+            print(f"physics: thermalised {k + 1}/{therm} sweeps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_therm = time.perf_counter() - t0
+    sums = torch.zeros((4, n_chains), dtype=torch.float64, device=b.device)
+    for k in range(meas):
+        b.sweep(1)
+        o = b.measure()
+        s = b.spin_structure(eps)
+        sums[0] += torch.from_numpy(o["kinetic"].copy()).to(b.device)
+        sums[1] += s
+        sums[2] += torch.from_numpy(o["double_occ"].copy()).to(b.device)
+        sums[3] += torch.from_numpy(o["density"].copy()).to(b.device)
+        if (k + 1) % 50 == 0:
+            print(f"physics: measured {k + 1}/{meas} sweeps", file=sys.stderr, flush=True)
+    o = b.measure()
+    wall = time.perf_counter() - t0
+    per_chain = (sums / meas).cpu().numpy()
+
+    def stat(v):
+        return float(v.mean()), float(v.std(ddof=1) / np.sqrt(len(v)))
+
+    ek, s_n, d, dens = (stat(per_chain[i]) for i in range(4))
+    s_l2 = (2.0 * s_n[0], 2.0 * s_n[1])          # (1/L^2) sum_ij = (N/L^2) (1/N) sum_ij, N = 2 L^2
+    s_m = (4.0 * s_n[0], 4.0 * s_n[1])           # moments m_i = n_i,up - n_i,dn = 2 s^z_i, 1/N
+    out = {"workload": w.name, "lattice": "honeycomb", "L": w.L, "n_sites": w.n_sites, "U": w.U,
+           "beta": w.beta, "dtau": w.dtau, "chains": n_chains, "thermalisation_sweeps": therm,
+           "measurement_sweeps": meas, "E_k": ek, "S_Gamma_1_over_N": s_n, "S_Gamma_1_over_L2": s_l2,
+           "S_Gamma_moments_1_over_N": s_m,
+           "double_occ": d, "density": dens,
+           "acceptance": float(o["accepted"].sum() / max(1, o["attempted"].sum())),
+           "flags": int(np.bitwise_or.reduce(o["flags"])), "max_drift": float(o["max_drift"].max()),
+           "near_ties": int(o["near_ties"].sum()), "seconds_thermalise": t_therm, "seconds_total": wall,
+           "paper_good_dqmc": PAPER_TABLE2}
+    for key, (mu, se) in (("E_k", ek), ("S_Gamma_1_over_N", s_n), ("S_Gamma_1_over_L2", s_l2),
+                          ("S_Gamma_moments_1_over_N", s_m)):
+        pm, pe = PAPER_TABLE2["E_k" if key == "E_k" else "S_Gamma"]
+        out[f"{key}_sigma_from_paper"] = (mu - pm) / float(np.hypot(se, pe))
+    b.close()
+    return out
+
+
 def fp32_wrap_error(w, n_chains: int, bound: float):
     """FP32-wrap error on fixed fields against the FP64 fresh G, per refresh interval."""
     from paper_2106_00712_amd.autotune import Autotuner
@@ -238,6 +298,10 @@ def main():
     ap.add_argument("--precision", default="fp64", help="with --workload: fp64 or fp32_wrap")
     ap.add_argument("--mixed", action="store_true",
                     help="only the mixed-size batch: honeycomb 6x6 + 12x12, FP32 wraps, one graph")
+    ap.add_argument("--physics", action="store_true",
+                    help="only the paper's honeycomb point (L=6, U=3.83, beta=6): E_k and S(Gamma)")
+    ap.add_argument("--therm", type=int, default=200, help="with --physics: thermalisation sweeps")
+    ap.add_argument("--meas", type=int, default=400, help="with --physics: measurement sweeps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +333,9 @@ def main():
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),
                           "phase_share": r["phase_share"]}))
+        return
+    if args.physics:
+        print(json.dumps(run_physics(args.chains or 256, args.therm, args.meas)))
         return
     if args.mixed:
         print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256)))

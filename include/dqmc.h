@@ -147,6 +147,15 @@ dqmc_status dqmc_graph_destroy(dqmc_graph* g);
  * (the outputs are written regardless). */
 dqmc_status dqmc_measure(dqmc_batch* b, dqmc_obs* obs, double* green, void* stream);
 
+/* Magnetic structure factor of every chain at G(0) (main text eq. (4): S(Q) = (1/N) sum_ij
+ * e^{-iQ.(r_i - r_j)} <s^z_i s^z_j>, s^z = (n_up - n_dn)/2), for a real form factor f:
+ * out[c] = (1/N) sum_ij f_i f_j <s^z_i s^z_j>, evaluated by Wick's theorem at chain c's field.
+ * Phases +-1 (a sublattice sign) give S(Q) directly; a complex phase e^{iQ.r} is the sum of the
+ * results for f = cos(Q.r) and f = sin(Q.r).
+ *   form: DEVICE double [N].   out: DEVICE double [n_chains].
+ * Asynchronous on the stream; same G(0) as dqmc_measure. */
+dqmc_status dqmc_spin_structure(dqmc_batch* b, const double* form, double* out, void* stream);
+
 /* Current fields into out (DEVICE int8 [n_chains][n_slices][N]). */
 dqmc_status dqmc_get_fields(dqmc_batch* b, int8_t* out, void* stream);
 

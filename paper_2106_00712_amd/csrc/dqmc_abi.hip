@@ -193,6 +193,43 @@ __global__ __launch_bounds__(NT) void measure_kernel(KArgs a, dqmc_obs* obs, dou
   }
 }
 
+// (1/N) sum_ij f_i f_j <s^z_i s^z_j> at G(0) by Wick's theorem (both spins independent at a fixed
+// field): (1/(4N)) [m^2 + sum_s (sum_i f_i^2 G^s_ii - sum_ij f_i f_j G^s_ij G^s_ji)] with
+// m = sum_i f_i (G^dn_ii - G^up_ii).  One block per chain.
+__global__ __launch_bounds__(NT) void spin_structure_kernel(KArgs a, const double* form, double* out) {
+  const int chain = blockIdx.x, tid = threadIdx.x;
+  const int n = a.n, np = a.np;
+  const double* G64 = (const double*)(a.base + (size_t)chain * a.stride + a.o_G64);
+  __shared__ double red[2][NW];
+  double m = 0, acc = 0;
+  for (int i = tid; i < n; i += NT) {
+    double f = form[i], gu = G64[i * np + i], gd = G64[(size_t)np * np + i * np + i];
+    m += f * (gd - gu);
+    acc += f * f * (gu + gd);
+  }
+  for (int e = tid; e < n * n; e += NT) {
+    int i = e / n, j = e - i * n;
+    double ff = form[i] * form[j];
+    if (ff == 0.0) continue;
+    for (int sp = 0; sp < 2; ++sp) {
+      const double* G = G64 + (size_t)sp * np * np;
+      acc -= ff * G[i * np + j] * G[j * np + i];
+    }
+  }
+  m = wave_sum(m);
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = m;
+    red[1][tid >> 6] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sm = 0, sa = 0;
+    for (int w = 0; w < NW; ++w) { sm += red[0][w]; sa += red[1][w]; }
+    out[chain] = (sm * sm + sa) / (4.0 * n);
+  }
+}
+
 __global__ void get_fields_kernel(KArgs a, int8_t* out) {
   const int chain = blockIdx.x;
   const int8_t* f = (const int8_t*)(a.base + (size_t)chain * a.stride + a.o_fields);
@@ -668,6 +705,15 @@ dqmc_status dqmc_measure(dqmc_batch* b, dqmc_obs* obs, double* green, void* stre
   HIP_TRY(hipStreamSynchronize(s));
   for (const dqmc_obs& o : h)
     if (o.flags) return fail(DQMC_ENUMERIC, "a chain raised a numerical flag");
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_spin_structure(dqmc_batch* b, const double* form, double* out, void* stream) {
+  if (!b || !form || !out) return fail(DQMC_EINVAL, "batch/form/out is NULL");
+  if (b->n_chains == 0) return DQMC_OK;
+  hipLaunchKernelGGL(spin_structure_kernel, dim3(b->n_chains), dim3(NT), 0, (hipStream_t)stream,
+                     b->args, form, out);
+  HIP_TRY(hipGetLastError());
   return DQMC_OK;
 }
 

@@ -56,6 +56,7 @@ _SIGS = {
     "dqmc_sweep_multi": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32, _vp]),
     "dqmc_measure": (_i32, [_vp, _vp, _vp, _vp]),
     "dqmc_get_fields": (_i32, [_vp, _vp, _vp]),
+    "dqmc_spin_structure": (_i32, [_vp, _vp, _vp, _vp]),
     "dqmc_destroy": (_i32, [_vp]),
     "dqmc_last_error": (ctypes.c_char_p, []),
     "dqmc_batch_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -239,6 +240,19 @@ class Batch:
             _check(st)
         o = np.frombuffer(obs.cpu().numpy().tobytes(), dtype=OBS_DTYPE)
         return (o, g) if green else o
+
+    def spin_structure(self, form, stream=None):
+        """(1/N) sum_ij f_i f_j <s^z_i s^z_j> of every chain at G(0) for a real form factor f
+        (length N); a device float64 tensor [n_chains], computed asynchronously on the stream."""
+        torch = self.torch
+        f = torch.as_tensor(np.asarray(form, dtype=np.float64)).to(self.device)
+        if f.numel() != self.n:
+            raise ValueError(f"form factor has {f.numel()} entries, the lattice {self.n} sites")
+        out = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_spin_structure(self._h, _ptr(f), _ptr(out), _stream(stream, self.device)))
+        self._form_keep = f
+        return out
 
     def fields(self, stream=None):
         torch = self.torch

@@ -32,11 +32,12 @@ def fock_operators(n_modes: int):
     return ops
 
 
-def fock_trotter(T: np.ndarray, U: float, dtau: float, n_slices: int):
+def fock_trotter(T: np.ndarray, U: float, dtau: float, n_slices: int, form=None):
     """Z and <O> at the slice boundary for the Trotterised Hubbard model of eq. (3).
 
     Modes: (i, up) -> i, (i, dn) -> N + i.  Returns Z = Tr[(e^{-dtau H_U} e^{-dtau H_k})^L],
-    double occupancy per site and kinetic energy per site, both inserted at the right end.
+    double occupancy per site and kinetic energy per site, both inserted at the right end; with a
+    real form factor f also (1/N) <(sum_i f_i s^z_i)^2>, s^z_i = (n_i,up - n_i,dn)/2.
     """
     N = T.shape[0]
     c = fock_operators(2 * N)
@@ -60,7 +61,10 @@ def fock_trotter(T: np.ndarray, U: float, dtau: float, n_slices: int):
     D = sum(n[i] @ n[N + i] for i in range(N)) / N
     docc = float(np.trace(P @ D)) / Z
     ekin = float(np.trace(P @ Hk)) / Z / N
-    return Z, docc, ekin
+    if form is None:
+        return Z, docc, ekin
+    Mz = sum(form[i] * 0.5 * (n[i] - n[N + i]) for i in range(N))
+    return Z, docc, ekin, float(np.trace(P @ Mz @ Mz)) / Z / N
 
 
 # ----------------------------------------------------------------------- enumeration

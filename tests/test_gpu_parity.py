@@ -148,6 +148,29 @@ def test_initial_green_and_logdet(dq):
         assert abs(obs["double_occ"][c] - ref[c]["double_occ"]) < 1e-12
 
 
+def test_spin_structure_form_factors(dq):
+    """Structure factor at G(0) for the sublattice sign, a uniform and a real cos/sin form factor
+    pair (S(Q) at a general Q is the sum of the two) against the oracle, to 1e-11."""
+    from oracle import spin_structure
+    w = di.WORKLOADS["square8x8_U4_b4"]
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    b = dq.Batch(m, w.seeds(3), w.fields(3))
+    _, oc = oracle_for(w, 3)
+    g = oc.green()
+    x = np.arange(64) % 8
+    y = np.arange(64) // 8
+    q = (2 * np.pi / 8) * np.array([1.0, 3.0])
+    forms = [di.staggered_sign("square", 8), np.ones(64), np.cos(q[0] * x + q[1] * y),
+             np.sin(q[0] * x + q[1] * y)]
+    for f in forms:
+        s = b.spin_structure(f).cpu().numpy()
+        for c in range(3):
+            ref = spin_structure(g[c, 0], g[c, 1], f)
+            assert abs(s[c] - ref) < 1e-11 * max(1.0, abs(ref)), (c, s[c], ref)
+    with pytest.raises(ValueError):
+        b.spin_structure(np.ones(63))
+
+
 # ------------------------------------------------------------------ trajectories
 def _trajectory_check(dq, w, n, sweeps, delay_rank=0, first=0):
     m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank)
@@ -156,7 +179,9 @@ def _trajectory_check(dq, w, n, sweeps, delay_rank=0, first=0):
     b.sweep(sweeps)
     oc.sweep(sweeps)
     obs = b.measure()
-    ref = oc.measure()
+    eps = di.staggered_sign(w.lattice, w.L)
+    s_af = b.spin_structure(eps).cpu().numpy()
+    ref = oc.measure(stagger=eps)
     f_gpu = b.fields().cpu().numpy()
     f_ref = oc.fields()
     for c in range(n):
@@ -166,6 +191,7 @@ def _trajectory_check(dq, w, n, sweeps, delay_rank=0, first=0):
         assert obs["accepted"][c] == ref[c]["accepted"]
         assert abs(obs["double_occ"][c] - ref[c]["double_occ"]) < 1e-9
         assert abs(obs["kinetic"][c] - ref[c]["kinetic"]) < 1e-9
+        assert abs(s_af[c] - ref[c]["spin_af"]) < 1e-9
         assert math.isclose(obs["logdet_up"][c], ref[c]["logdet_up"], rel_tol=1e-9)
         assert obs["flags"][c] == 0
         assert obs["max_drift"][c] < 1e-6
@@ -224,6 +250,12 @@ def test_rejects_small_workspace(dq):
 
 # ------------------------------------------------------------------ other sizes
 SQUARE6 = di.Workload("square6x6_U4_b2", 7, "square", 6, 4.0, 2.0, 0.1, 2, 2, 10)
+SQUARE2 = di.Workload("square2x2_U4_b2", 8, "square", 2, 4.0, 2.0, 0.1, 2, 5, 5)
+
+
+def test_trajectory_parity_square2x2(dq):
+    """N = 4, fewer sites than one delayed-update block."""
+    _trajectory_check(dq, SQUARE2, 2, 5)
 
 
 def test_trajectory_parity_square6x6_padded(dq):

@@ -327,23 +327,6 @@ def test_chain_statistics_match_enumeration():
 
 
 # ------------------------------------------------------------------ spin structure factor
-def _fock_spin_structure(T, U, dtau, n_slices, eps):
-    """(1/N) <(sum_i eps_i s^z_i)^2> in the Trotterised Fock space (exact for the discrete model)."""
-    N = T.shape[0]
-    c = ex.fock_operators(2 * N)
-    cd = [op.T for op in c]
-    n = [cd[m] @ c[m] for m in range(2 * N)]
-    dim = c[0].shape[0]
-    I = np.eye(dim)
-    Hk = sum(T[i, j] * cd[s * N + i] @ c[s * N + j]
-             for s in range(2) for i in range(N) for j in range(N) if T[i, j] != 0.0)
-    Hu = sum(U * (n[i] - 0.5 * I) @ (n[N + i] - 0.5 * I) for i in range(N))
-    import scipy.linalg as sla
-    P = np.linalg.matrix_power(np.diag(np.exp(-dtau * np.diag(Hu))) @ sla.expm(-dtau * Hk), n_slices)
-    Mz = sum(eps[i] * 0.5 * (n[i] - n[N + i]) for i in range(N))
-    return float(np.trace(P @ Mz @ Mz) / np.trace(P)) / N
-
-
 @pytest.mark.parametrize("form", ["staggered", "uniform", "random"])
 def test_spin_structure_equals_fock_trace(form):
     """The Wick estimator averaged over all HS fields of a 2x2 lattice equals the Fock-space trace
@@ -357,7 +340,7 @@ def test_spin_structure_equals_fock_trace(form):
     fields, w, Gu, Gd = ex.enumerate_fields(T, U, dtau, Lt)
     vals = np.array([spin_structure(Gu[k], Gd[k], eps) for k in range(fields.shape[0])])
     hs = float(np.sum(w * vals) / np.sum(w))
-    fock = _fock_spin_structure(T, U, dtau, Lt, eps)
+    fock = ex.fock_trotter(T, U, dtau, Lt, form=eps)[3]
     assert math.isclose(hs, fock, rel_tol=1e-11), (hs, fock)
 
 
