@@ -1,4 +1,5 @@
-"""CPU FP64 oracle of the DQMC sweep: TEST INFRASTRUCTURE ONLY.
+"""CPU FP64 oracles of the DQMC sweep and of the batched Ising Metropolis sweep
+(`oracle.ising_oracle`): TEST INFRASTRUCTURE ONLY.
 
 Plain, slow and written to be checked against the paper by eye.  It may be imported only by
 tests/, by __graft_entry__.smoke() and by the cpu_baseline leg of bench.py.  It shares no code
