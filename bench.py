@@ -250,6 +250,68 @@ def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
     return out
 
 
+# Good-MC column of the paper's Table 1 (square Ising, L = 16, T = 2.269 J)
+PAPER_TABLE1 = {"abs_M": (0.713, 0.003), "E": (-1.453, 0.002)}
+# Algorithmic 32-bit lane operations per Ising update: a quarter of one Philox4x64-10 block
+# (10 rounds of two 64x64->128 products as 4 partial 32x32->64 products each = 8 multiplies + 6
+# carry adds, two 64-bit xor pairs and the key bump: 40 per round) = 100, the uniform (shift,
+# convert, scale) 6, the flip (4 neighbour loads, 3 adds, product, table select, compare,
+# store) 14.
+ISING_OPS_PER_UPDATE = 120
+# Full-rate 32-bit VALU lane operations of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def run_ising(L: int, T: float, n_chains: int, therm: int, meas: int, ac_len: int,
+              conv_len: int = 300, seed_cfg: int = 7):
+    """Table 1's Good-MC numbers from independent chains, the Fig. 3 convergence of |M| from
+    random starts, the autocorrelation of M (supplement eq. (5)) and the sweep throughput."""
+    import torch
+    from paper_2106_00712_amd import analysis, ising
+    n = L * L
+    b = ising.IsingBatch(L, T, di.chain_seeds(seed_cfg, n_chains))
+    conv = b.sweep(conv_len, measure=False, series=True)
+    am = np.abs(conv[:, :, 0].double().cpu().numpy()) / n
+    curve, curve_se = analysis.convergence_curve(am)
+    b.sweep(max(0, therm - conv_len), measure=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.sweep(meas, measure=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    st = b.stats()
+    nm = st["n_meas"].astype(np.float64)
+    abs_m = analysis.mean_and_error(st["sum_abs_m"] / nm / n)
+    e = analysis.mean_and_error(-st["sum_bond"] / nm / n)
+    m2 = analysis.mean_and_error(st["sum_m2"] / nm / n ** 2)
+    ser = b.sweep(ac_len, measure=False, series=True)[:, :, 0].double().cpu().numpy()
+    a = analysis.autocorrelation(ser, min(400, ac_len // 4))
+    a_abs = analysis.autocorrelation(np.abs(ser), min(400, ac_len // 4))
+    ups = n_chains * meas * n / sec
+    out = {"workload": f"ising{L}x{L}_T{T:g}", "L": L, "T": T, "J": 1.0, "chains": n_chains,
+           "thermalisation_sweeps": therm, "measurement_sweeps": meas,
+           "abs_M": abs_m, "E": e, "M2": m2, "paper_good_mc": PAPER_TABLE1,
+           "acceptance": float(st["accepted"].sum() / (st["sweeps_done"].sum() * n)),
+           "convergence_abs_M": {str(k): float(curve[k - 1]) for k in (1, 10, 30, 50, 100, 150, 200, 300)
+                                 if k <= conv_len},
+           "convergence_abs_M_se": {str(k): float(curve_se[k - 1]) for k in (1, 30, 100, 300) if k <= conv_len},
+           "autocorr_M": {str(t): float(a[t]) for t in (1, 10, 50, 100, 200, 400) if t < len(a)},
+           "tau_int_M": analysis.integrated_time(a), "tau_int_abs_M": analysis.integrated_time(a_abs),
+           "ms_per_sweep": sec * 1e3 / meas, "updates_per_s": ups,
+           "roofline": {"bound": "alu", "achieved": ups * ISING_OPS_PER_UPDATE / 1e12,
+                        "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-op/s",
+                        "frac": ups * ISING_OPS_PER_UPDATE / PEAK_VALU_LANE_OPS, "traffic": None}}
+    if L == 16 and abs(T - 2.269) < 1e-12:
+        for key in ("abs_M", "E"):
+            pm, pe = PAPER_TABLE1[key]
+            out[f"{key}_sigma_from_paper"] = (out[key][0] - pm) / float(np.hypot(out[key][1], pe))
+    b.close()
+    return out
+
+
 def fp32_wrap_error(w, n_chains: int, bound: float):
     """FP32-wrap error on fixed fields against the FP64 fresh G, per refresh interval."""
     from paper_2106_00712_amd.autotune import Autotuner
@@ -302,6 +364,9 @@ def main():
                     help="only the paper's honeycomb point (L=6, U=3.83, beta=6): E_k and S(Gamma)")
     ap.add_argument("--therm", type=int, default=200, help="with --physics: thermalisation sweeps")
     ap.add_argument("--meas", type=int, default=400, help="with --physics: measurement sweeps")
+    ap.add_argument("--ising", action="store_true",
+                    help="only the Ising workload: Table 1 at L=16, T=2.269, plus L=32 dynamics")
+    ap.add_argument("--ising-meas", type=int, default=20000, help="with --ising: measured sweeps at L=16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -333,6 +398,12 @@ def main():
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),
                           "phase_share": r["phase_share"]}))
+        return
+    if args.ising:
+        r16 = run_ising(16, 2.269, args.chains or 1024, 2000, args.ising_meas, 4000)
+        print(json.dumps(r16), flush=True)
+        r32 = run_ising(32, 2.269, 256, 4000, 4000, 8000)
+        print(json.dumps(r32), flush=True)
         return
     if args.physics:
         print(json.dumps(run_physics(args.chains or 256, args.therm, args.meas)))

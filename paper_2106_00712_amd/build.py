@@ -7,8 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libdqmc.so")
-SOURCES = [os.path.join(HERE, "csrc", "dqmc_abi.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "dqmc_device.hpp"), os.path.join(ROOT, "include", "dqmc.h")]
+SOURCES = [os.path.join(HERE, "csrc", "dqmc_abi.hip"), os.path.join(HERE, "csrc", "ising.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "dqmc_device.hpp"), os.path.join(ROOT, "include", "dqmc.h"),
+           os.path.join(ROOT, "include", "ising.h")]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 arithmetic (v_pk_*_f32).
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

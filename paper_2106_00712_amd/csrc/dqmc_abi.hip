@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dqmc.h"
+#include "dqmc_error.hpp"
 #include "dqmc_device.hpp"
 #include "dqmc_fast.hpp"
 
@@ -532,6 +533,9 @@ SidePool& side_pool() {
 }
 
 }  // namespace
+
+// Error message shared with the other translation units of the library (dqmc_last_error).
+dqmc_status dqmc::set_error(dqmc_status s, const std::string& msg) { return fail(s, msg); }
 
 // ------------------------------------------------------------------------ C ABI
 extern "C" {

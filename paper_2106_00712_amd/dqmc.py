@@ -72,6 +72,14 @@ _SIGS = {
     "dqmc_debug_phase_ticks": (_i32, [_vp, _vp, _vp]),
     "dqmc_debug_philox": (_i32, [_u64, _u64, _u64, _u64, _u64, _u64, _i32, _vp, _vp]),
     "dqmc_debug_mfma": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    # include/ising.h
+    "ising_workspace_bytes": (_sz, [_i32, _i32]),
+    "ising_init": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.c_double, ctypes.c_double, _i32, _vp,
+                          ctypes.POINTER(_u64), _vp, _sz, _vp]),
+    "ising_sweep": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "ising_stats": (_i32, [_vp, _vp, _vp]),
+    "ising_get_spins": (_i32, [_vp, _vp, _vp]),
+    "ising_destroy": (_i32, [_vp]),
 }
 
 
