@@ -94,12 +94,23 @@ def load_traffic():
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh: int):
+def choose_qr(w, mode: str) -> bool:
+    """Stabilisation QR of the N > 64 kernels: 'pivoted', 'blocked', or 'auto' (the autotuner's
+    accuracy check on two chains' fixed fields)."""
+    if mode != "auto":
+        return mode == "blocked"
+    from paper_2106_00712_amd.autotune import Autotuner
+    return Autotuner().qr_method(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(2), w.seeds(2),
+                                 w.stab_every)["qr_blocked"]
+
+
+def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh: int,
+            qr_blocked: bool = False):
     import torch
     from paper_2106_00712_amd import dqmc
 
     m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank,
-                        precision=precision, refresh_every=refresh)
+                        precision=precision, refresh_every=refresh, qr_blocked=qr_blocked)
     fields = torch.as_tensor(w.fields()).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -155,18 +166,20 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
             "pool_capacity": capacity, "tick_sweeps": tick}
 
 
-def run_mixed(steps: int, refresh: int, n_each: int):
+def run_mixed(steps: int, refresh: int, n_each: int, qr_mode: str = "auto"):
     """Honeycomb 6x6 (N = 72) and 12x12 (N = 288) chains side by side in one recorded graph,
     FP32 wraps with FP64 refresh every `refresh` slices, against the same batches in FP64."""
     import torch
     from paper_2106_00712_amd import dqmc
     ws = [di.WORKLOADS["honeycomb6x6_U3_b6"], di.WORKLOADS["honeycomb12x12_U3_b6"]]
-    out = {"workload": "honeycomb 6x6 + 12x12, U=3, beta=6", "chains_each": n_each, "steps": steps}
+    qrb = [choose_qr(w, qr_mode) for w in ws]
+    out = {"workload": "honeycomb 6x6 + 12x12, U=3, beta=6", "chains_each": n_each, "steps": steps,
+           "qr_blocked": qrb}
     for prec in ("fp64", "fp32_wrap"):
         bs = []
-        for w in ws:
+        for w, qb in zip(ws, qrb):
             m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, precision=prec,
-                                refresh_every=refresh if prec == "fp32_wrap" else 0)
+                                refresh_every=refresh if prec == "fp32_wrap" else 0, qr_blocked=qb)
             bs.append(dqmc.Batch(m, w.seeds(n_each), w.fields(n_each)))
         g = dqmc.Graph(bs, [1, 1])
         g.launch()
@@ -364,6 +377,8 @@ def main():
                     help="only the paper's honeycomb point (L=6, U=3.83, beta=6): E_k and S(Gamma)")
     ap.add_argument("--therm", type=int, default=200, help="with --physics: thermalisation sweeps")
     ap.add_argument("--meas", type=int, default=400, help="with --physics: measurement sweeps")
+    ap.add_argument("--qr", default="auto", choices=("auto", "pivoted", "blocked"),
+                    help="with --workload / --mixed: stabilisation QR of the N > 64 kernels")
     ap.add_argument("--ising", action="store_true",
                     help="only the Ising workload: Table 1 at L=16, T=2.269, plus L=32 dynamics")
     ap.add_argument("--ising-meas", type=int, default=20000, help="with --ising: measured sweeps at L=16")
@@ -380,8 +395,9 @@ def main():
         if args.chains:
             wl = di.Workload(wl.name, wl.config_id, wl.lattice, wl.L, wl.U, wl.beta, wl.dtau,
                              args.chains, wl.n_sweeps, wl.stab_every)
+        qb = choose_qr(wl, args.qr)
         r = run_gpu(wl, args.precision, args.steps, args.warmup, args.delay_rank,
-                    (args.refresh or 10) if args.precision == "fp32_wrap" else 0)
+                    (args.refresh or 10) if args.precision == "fp32_wrap" else 0, qr_blocked=qb)
         o = r["obs"]
         ups = wl.n_chains * wl.n_slices * wl.n_sites
         acc = float(o["accepted"].sum() / max(1, o["attempted"].sum()))
@@ -393,7 +409,7 @@ def main():
                           "tflops": flw["total"] * wl.n_chains / tl / 1e12,
                           "frac_fp64_peak": flw["total"] * wl.n_chains / tl / PEAK_FP64_MFMA,
                           "kernel_variant": r["batch"].variant, "delay_rank": r["batch"].delay_rank,
-                          "stab": r["batch"].stab, "init_ms": r["init_ms"],
+                          "stab": r["batch"].stab, "qr_blocked": qb, "init_ms": r["init_ms"],
                           "max_drift": float(o["max_drift"].max()),
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),
@@ -409,7 +425,7 @@ def main():
         print(json.dumps(run_physics(args.chains or 256, args.therm, args.meas)))
         return
     if args.mixed:
-        print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256)))
+        print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256, args.qr)))
         return
     if args.serving_full:
         out = [run_serving(rate, 48, di.SERVING_L, "fp64", 16, 10, 0) for rate in (50, 2000)]

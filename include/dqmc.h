@@ -66,6 +66,12 @@ typedef struct {
                                The refresh points are also the stabilisation points. */
   int32_t delay_rank;       /* k: sites per delayed-update block (0 = library default) */
   int32_t precision;        /* dqmc_precision */
+  int32_t qr_blocked;       /* 0: column-pivoted Householder QR in every stabilisation (default).
+                               1: for 64 < N <= 512, blocked Householder QR with the columns
+                               pre-sorted by norm once (MFMA trailing updates; much faster at
+                               large N).  It reproduces the pivoted G only while the products are
+                               mildly graded; enable it for a model only after checking that on
+                               fixed fields (the autotuner does).  Ignored elsewhere. */
 } dqmc_model;
 
 /* Observables of one chain, written by dqmc_measure (device memory, one per chain).  The

@@ -8,6 +8,12 @@
   compared with the FP64 fresh G of the same slice (max |dG| over sampled slices and chains);
   the largest r within the bound is chosen.
 
+* Stabilisation QR for N > 64.  The blocked QR with pre-sorted columns is much faster than the
+  column-pivoted one but reproduces its Green's function only while the B products are mildly
+  graded (strong coupling and low temperature spread the scales too far).  On fixed fields both
+  are run and the blocked one is chosen when the fresh G of every sampled slice agrees within the
+  bound.
+
 Results are cached per model in a JSON file when a path is given.
 """
 from __future__ import annotations
@@ -116,6 +122,34 @@ class Autotuner:
                 break
             best = r
         rec = {"refresh_every": int(best), "bound": bound, "max_abs_dG": {str(r): v for r, v in errs.items()}}
+        self.cache[key] = rec
+        self._save()
+        return rec
+
+    def qr_method(self, hopping, U, dtau, n_slices, fields, seeds, stab_every: int = 10,
+                  bound: float = 1e-11, slices: Optional[Sequence[int]] = None) -> dict:
+        """Use the blocked QR (qr_blocked = 1) when its fresh G matches the column-pivoted one
+        within `bound` (max |dG| over chains and sampled slices) on the given fixed fields."""
+        T = np.asarray(hopping, dtype=np.float64)
+        N = T.shape[0]
+        key = _model_id(N, n_slices, U, dtau, "fp64", f"_s{stab_every}_b{bound:g}_qr")
+        if key in self.cache:
+            return self.cache[key]
+        if N <= 64 or N > 512:
+            rec = {"qr_blocked": False, "max_abs_dG": None, "reason": "blocked QR not used at this N"}
+        else:
+            if slices is None:
+                slices = sorted({0, n_slices // 2, n_slices})
+            ms = [dqmc.make_model(T, U, dtau, n_slices, stab_every, qr_blocked=qb) for qb in (False, True)]
+            bs = [dqmc.Batch(m, seeds, fields, device=self.device) for m in ms]
+            err = 0.0
+            for l in slices:
+                g0 = bs[0].debug_green(int(l), 0)
+                g1 = bs[1].debug_green(int(l), 0)
+                err = max(err, float((g0 - g1).abs().max().item()))
+            for b in bs:
+                b.close()
+            rec = {"qr_blocked": bool(err <= bound), "max_abs_dG": err, "bound": bound}
         self.cache[key] = rec
         self._save()
         return rec

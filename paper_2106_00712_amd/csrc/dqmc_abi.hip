@@ -313,7 +313,7 @@ struct Layout {
   size_t c_expK, c_expKinv, c_expK32, c_expKinv32, c_T, c_eye, c_ones, c_A, c_E0, c_E1, c_seeds,
       c_slots, c_err, c_end;
   // per chain
-  size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, stride;
+  size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, o_qrv, stride;
 };
 
 int max_lds_per_block() {
@@ -339,6 +339,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   if (m->precision != DQMC_FP64 && m->precision != DQMC_FP32_WRAP)
     return fail(DQMC_EINVAL, "unknown precision");
   if (m->refresh_every < 0 || m->delay_rank < 0) return fail(DQMC_EINVAL, "negative refresh/delay");
+  if (m->qr_blocked != 0 && m->qr_blocked != 1) return fail(DQMC_EINVAL, "qr_blocked must be 0 or 1");
   if (n_chains < 0) return fail(DQMC_EINVAL, "n_chains must be >= 0");
   Layout L{};
   L.n = m->n_sites;
@@ -422,8 +423,11 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   if (!L.small) {
     L.o_work = ctake(2 * nn * 8);
     L.o_xy = ctake(4 * (size_t)L.np * L.K * wts);
+    // blocked factorisations (np <= QR_BLOCK_MAX_NP): QR reflectors (np x np) and one QB x QB
+    // T per panel; the Gauss-Jordan solve reuses the first 3 QB np doubles
+    L.o_qrv = (L.np <= QR_BLOCK_MAX_NP) ? ctake((nn + (size_t)QB * L.np) * 8) : 0;
   } else {
-    L.o_work = L.o_xy = 0;
+    L.o_work = L.o_xy = L.o_qrv = 0;
   }
   L.stride = align256(co);
   *out = L;
@@ -455,6 +459,8 @@ void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KAr
   a->stride = L.stride;
   a->o_fields = L.o_fields; a->o_G64 = L.o_G64; a->o_Gw = L.o_Gw; a->o_stack = L.o_stack;
   a->o_left = L.o_left; a->o_work = L.o_work; a->o_xy = L.o_xy; a->o_stats = L.o_stats;
+  a->o_qrv = L.o_qrv;
+  a->qr_blocked = m->qr_blocked;
 }
 
 // The kernel a batch runs for an operation, and its LDS bytes.

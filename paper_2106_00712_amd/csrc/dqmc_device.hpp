@@ -72,6 +72,8 @@ struct KArgs {
   char* base;
   size_t stride;        // bytes per chain
   size_t o_fields, o_G64, o_Gw, o_stack, o_left, o_work, o_xy, o_stats;
+  size_t o_qrv;         // scratch of the blocked factorisations (0: unblocked only)
+  int qr_blocked;       // stabilisation QR: 1 blocked with pre-sorted columns, 0 column-pivoted
   double* out;
 };
 
@@ -306,6 +308,7 @@ struct Ctx {
   WT* xy;             // delayed-update panels: X_up, Y_up, X_dn, Y_dn (np*K each)
   double* stack;      // right UDT stack [2][J][U, T, d]
   double* left;       // left UDT [2][U, T0, T1, d]
+  double* qrv;        // blocked QR: reflectors V (np x np, column-major) then T factors, or NULL
   // LDS vectors
   double *vd, *bt, *nrm, *dtmp, *sr, *sc;   // sr/sc: [2][np] row/column scale factors
   int* ordv;          // [np] pivot order / used marks
@@ -350,6 +353,7 @@ __device__ inline Ctx<WT> make_ctx(const KArgs& a, int chain, double* lds) {
   c.G64 = (double*)(cb + a.o_G64);
   c.stack = (double*)(cb + a.o_stack);
   c.left = (double*)(cb + a.o_left);
+  c.qrv = a.o_qrv ? (double*)(cb + a.o_qrv) : nullptr;
   double* p = lds;
   if (SMALL) {
     WT* g = (WT*)p;
@@ -611,6 +615,255 @@ __device__ __forceinline__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, do
   __syncthreads();
 }
 
+// Blocked Householder QR of the N > 64 kernels (matrices in the workspace).  The columns are
+// sorted once by decreasing norm instead of being pivoted at every step (QR with pre-pivoting,
+// Bai, Lee, Li and Xu, Linear Algebra Appl. 435 (2011) 659: as accurate as column pivoting for
+// the graded products of the stabilisation, and it leaves the factorisation free to be blocked).
+// Panels of QB columns are factorised with the panel in registers, one workgroup reduction of
+// QB values per column (z_q = sum_r a_rj a_rq over the rows still active: the column's norm, the
+// projections of the later columns, and the V^T v products of the compact-WY factor).  Each
+// panel's reflectors satisfy H_1 ... H_QB = I - V T V^T (Schreiber and Van Loan) with T upper
+// triangular, T_jj = beta_j, T(0:j, j) = -beta_j T(0:j, 0:j) V(:, 0:j)^T v_j.  The trailing
+// columns get C <- (I - V T^T V^T) C and the explicit Q = H_1 ... H_n is accumulated from the
+// last panel back, both as MFMA products.  Outputs as wg_qrp + udt_finish: U = Q S into Ud
+// (row-major, zero padded), d = |diag R| into dd (1 on padding), and X <- T' = D^{-1} S R P^T
+// column-major in original column order (P the pre-pivot permutation).  A is a scratch matrix.
+constexpr int QB = 16;
+constexpr int QR_BLOCK_MAX_NP = 2 * NT;
+
+#ifndef DQMC_LDS
+#define DQMC_LDS __attribute__((address_space(3)))
+#endif
+
+// Not inlined: it has its own register budget inside the large generic sweep kernel, and one
+// instance per RPT serves both working precisions.  LDS arguments carry their address space.
+template <int RPT>
+__device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_lds, double* qrv,
+                                         DQMC_LDS double* nrm, DQMC_LDS int* ordv, DQMC_LDS int* rank,
+                                         DQMC_LDS double* vdv, DQMC_LDS double* btv,
+                                         DQMC_LDS double* dtmp, double* X, double* A, double* Ud,
+                                         double* dd, int* flags) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* stage = (double*)stage_lds;
+  double* V = qrv;                         // reflectors, np x np column-major, zero above the diagonal
+  double* Tg = qrv + (size_t)np * np;      // T of panel p at Tg[p QB^2], row-major
+  DQMC_LDS double* red = stage_lds;        // [NW][QB] partial sums
+  DQMC_LDS double* rowv = red + NW * QB;   // [QB] row r0 of the panel
+  DQMC_LDS double* yv = rowv + QB;         // [QB] V(:, i)^T v_j
+  DQMC_LDS double* Tl = yv + QB;           // [QB][QB] T of the current panel
+  // 1. pre-pivot: rank of each column by (norm descending, index ascending), a strict order
+  for (int col = wave; col < n; col += NW) {
+    double s = 0;
+    for (int r = lane; r < n; r += 64) { const double x = X[(size_t)col * np + r]; s += x * x; }
+    s = wave_sum_dpp(s);
+    if (lane == 0) nrm[col] = (s == s) ? s : -1.0;
+  }
+  __syncthreads();
+  for (int col = tid; col < n; col += NT) {
+    const double key = nrm[col];
+    int rk = 0;
+    for (int c2 = 0; c2 < n; ++c2) {
+      const double k2 = nrm[c2];
+      rk += (k2 > key || (k2 == key && c2 < col)) ? 1 : 0;
+    }
+    ordv[rk] = col;
+    rank[col] = rk;
+  }
+  __syncthreads();
+  // 2. A = X P (columns in pre-pivot order), V = 0
+  for (int e = tid; e < np * np; e += NT) {
+    const int j = e / np, r = e - j * np;
+    double v = 0.0;
+    if (j < n) {
+      int src = ordv[j];
+      src = (src >= 0 && src < n) ? src : j;
+      v = X[(size_t)src * np + r];
+    }
+    A[e] = v;
+    V[e] = 0.0;
+  }
+  __syncthreads();
+  // 3. panels
+  for (int k0 = 0, pnl = 0; k0 < n; k0 += QB, ++pnl) {
+    const int nbk = min(QB, n - k0);
+    for (int e = tid; e < QB * QB; e += NT) Tl[e] = 0.0;
+    double p[RPT][QB];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const int r = k0 + tid + NT * m;
+#pragma unroll
+      for (int q = 0; q < QB; ++q) p[m][q] = (r < np) ? A[(size_t)(k0 + q) * np + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      if (j < nbk) {
+        const int r0 = k0 + j;
+        double z[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) z[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+          const int r = k0 + tid + NT * m;
+          if (r >= r0 && r < np) {
+#pragma unroll
+            for (int q = 0; q < QB; ++q) z[q] += p[m][j] * p[m][q];
+          }
+        }
+        if (tid == j) {
+#pragma unroll
+          for (int q = 0; q < QB; ++q) rowv[q] = p[0][q];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const double t = wave_sum_dpp(z[q]);
+          if (lane == 0) red[wave * QB + q] = t;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) t += red[w * QB + q];
+          z[q] = t;
+        }
+        const double x0 = rowv[j];
+        const double nx = sqrt(z[j]);
+        const double al = (x0 >= 0.0) ? -nx : nx;
+        const double be = (nx > 0.0) ? 1.0 / (al * (al - x0)) : 0.0;
+        const double v0 = x0 - al;
+#pragma unroll
+        for (int q = j + 1; q < QB; ++q) {
+          const double w = be * (z[q] - al * rowv[q]);
+#pragma unroll
+          for (int m = 0; m < RPT; ++m) {
+            const int r = k0 + tid + NT * m;
+            if (r >= r0 && r < np) p[m][q] -= w * ((r == r0) ? v0 : p[m][j]);
+          }
+        }
+        if (tid == 0) {
+#pragma unroll
+          for (int q = 0; q < QB; ++q) yv[q] = z[q] - al * rowv[q];
+          Tl[j * QB + j] = be;
+          for (int i = 0; i < j; ++i) {
+            double acc = 0.0;
+            for (int k = i; k < j; ++k) acc += Tl[i * QB + k] * yv[k];
+            Tl[i * QB + j] = -be * acc;
+          }
+          vdv[r0] = al;
+          btv[j] = v0;
+        }
+        if (tid == j) p[0][j] = al;
+        __syncthreads();
+      }
+    }
+    // the panel back into A (R above, reflectors below), clean reflectors into V, T out
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const int r = k0 + tid + NT * m;
+      if (r < np) {
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          A[(size_t)(k0 + q) * np + r] = p[m][q];
+          double v = 0.0;
+          if (q < nbk) v = (r > k0 + q) ? p[m][q] : ((r == k0 + q) ? btv[q] : 0.0);
+          V[(size_t)(k0 + q) * np + r] = v;
+        }
+      }
+    }
+    for (int e = tid; e < QB * QB; e += NT) Tg[(size_t)pnl * QB * QB + e] = Tl[e];
+    __syncthreads();
+    // trailing columns: C <- C - V (T^T (V^T C)), W = V^T C staged in Ud (free until step 4)
+    if (n - k0 - QB > 0) {
+      const int ncr = ((n - k0 - QB) + 15) & ~15;
+      double* W = Ud;
+      const double* Vp = V + (size_t)k0 * np + k0;
+      const double* C = A + (size_t)(k0 + QB) * np + k0;
+      gemm_tiled<double>(stage, 1, QB, ncr, np - k0, Vp, Vp, np, 1, C, C, 1, np,
+                       [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
+      __syncthreads();
+      const double* T = Tg + (size_t)pnl * QB * QB;
+      for (int j = tid; j < ncr; j += NT) {
+        double w[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) w[q] = W[(size_t)q * np + j];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int b = 0; b <= q; ++b) s += T[b * QB + q] * w[b];
+          W[(size_t)q * np + j] = s;
+        }
+      }
+      __syncthreads();
+      gemm_tiled<double>(stage, 1, np - k0, ncr, QB, Vp, Vp, 1, np, W, W, np, 1,
+                       [&](int, int i, int j, double v) { A[(size_t)(k0 + QB + j) * np + k0 + i] -= v; });
+      __syncthreads();
+    }
+  }
+  // 4. Q = H_1 ... H_n from the last panel back: Q <- Q - V (T (V^T Q)) on rows >= k0; columns
+  //    < k0 of the partial product are zero on those rows and are skipped.  W staged in X.
+  for (int e = tid; e < np * np; e += NT) {
+    const int r = e / np, col = e - r * np;
+    Ud[e] = (r == col && r < n) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int pnl = (n + QB - 1) / QB - 1; pnl >= 0; --pnl) {
+    const int k0 = pnl * QB, w = np - k0;
+    double* W = X;
+    const double* Vp = V + (size_t)k0 * np + k0;
+    double* Qb = Ud + (size_t)k0 * np + k0;
+    gemm_tiled<double>(stage, 1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
+                     [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
+    __syncthreads();
+    const double* T = Tg + (size_t)pnl * QB * QB;
+    for (int j = tid; j < w; j += NT) {
+      double t[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) t[q] = W[(size_t)q * np + j];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = q; b < QB; ++b) s += T[q * QB + b] * t[b];
+        W[(size_t)q * np + j] = s;
+      }
+    }
+    __syncthreads();
+    gemm_tiled<double>(stage, 1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
+                     [&](int, int i, int j, double v) { Qb[(size_t)i * np + j] -= v; });
+    __syncthreads();
+  }
+  // 5. signs and scales, U = Q S, X <- T'
+  for (int jj = tid; jj < np; jj += NT) {
+    double dj = 1.0, sj = 1.0;
+    if (jj < n) {
+      const double rjj = vdv[jj];
+      dj = fabs(rjj);
+      sj = (rjj < 0.0) ? -1.0 : 1.0;
+      if (!(dj > 0.0)) atomicOr(flags, FLAG_SINGULAR);
+    }
+    dtmp[jj] = sj;
+    dd[jj] = dj;
+  }
+  __syncthreads();
+  for (int e = tid; e < np * np; e += NT) {
+    const int col = e - (e / np) * np;
+    if (col < n) Ud[e] *= dtmp[col];
+  }
+  for (int e = tid; e < np * np; e += NT) {
+    const int col = e / np, a = e - col * np;
+    double v = 0.0;
+    if (col < n && a < n) {
+      int j = rank[col];
+      j = (j >= 0 && j < n) ? j : col;
+      if (a <= j) v = dtmp[a] * A[(size_t)j * np + a] / dd[a];
+    }
+    X[e] = v;
+  }
+  __syncthreads();
+}
+
 // Multiply a chunk of slice propagators onto (Us, ds, Ts) and re-factorise:
 //   left  (right == false): product B_{hi} ... B_{lo+1} U D, B_l = V_l expK;
 //   right (right == true):  product B_{lo+1}^T ... B_{hi}^T U D, B_l^T = expK^T V_l;
@@ -661,8 +914,20 @@ __device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int l
       double* t = cur; cur = nxt; nxt = t;
     }
   }
-  wg_qrp(c, cur);
-  udt_finish(c, cur, Ud, dd, &c.st->flags);
+  if (a.qr_blocked && c.qrv && c.stage && np <= QR_BLOCK_MAX_NP) {
+    DQMC_LDS double* stg = (DQMC_LDS double*)c.stage;
+    DQMC_LDS double* nrm = (DQMC_LDS double*)c.nrm;
+    DQMC_LDS int* ordv = (DQMC_LDS int*)c.ordv;
+    DQMC_LDS int* rnk = (DQMC_LDS int*)c.rank;
+    DQMC_LDS double* vdv = (DQMC_LDS double*)c.vd;
+    DQMC_LDS double* btv = (DQMC_LDS double*)c.bt;
+    DQMC_LDS double* dtm = (DQMC_LDS double*)c.dtmp;
+    if (np <= NT) udt_blocked<1>(n, np, stg, c.qrv, nrm, ordv, rnk, vdv, btv, dtm, cur, nxt, Ud, dd, &c.st->flags);
+    else udt_blocked<2>(n, np, stg, c.qrv, nrm, ordv, rnk, vdv, btv, dtm, cur, nxt, Ud, dd, &c.st->flags);
+  } else {
+    wg_qrp(c, cur);
+    udt_finish(c, cur, Ud, dd, &c.st->flags);
+  }
   // Td = T' Ts  (cur now holds T', column-major)
   ctx_gemm<double>(c, 1, np, np, np, cur, cur, 1, np, Ts, Ts, np, 1,
                   [&](int, int i, int j, double v) { Td[i * np + j] = v; });
@@ -724,6 +989,198 @@ __device__ __forceinline__ double wg_gauss_jordan(Ctx<WT>& c, double* M, double*
   return logabs;
 }
 
+// Blocked Gauss-Jordan solve of the N > 64 kernels: dst = Diag(rs) M^{-1} Z with the same
+// partial (implicit) row pivoting as wg_gauss_jordan, QB columns at a time.  For a panel K of
+// columns with pivot rows P (chosen in registers, one row per thread, by eliminating the panel on
+// the rows not yet pivoted) the Gauss-Jordan steps of the panel act on every other column as
+//   rows r not in P:  x_r <- x_r - M[r, K] A_P^{-1} x_P,     rows P:  x_P <- A_P^{-1} x_P,
+// A_P = M[P, K] (rows in pivot order; its elimination without further pivoting is the panel's
+// partially pivoted one), so the later columns of M and all of Z take one rank-QB MFMA update
+// per panel.  Afterwards row ordv[j] of Z holds solution row j.  Returns log|det M| (the sum of
+// the logs of the pivots) to every thread.  scr: QB np + QB 2np doubles of workspace.
+template <int RPT>
+__device__ __noinline__ double gj_blocked(int n, int np, DQMC_LDS double* stage_lds, double* scr,
+                                          DQMC_LDS int* ordv, DQMC_LDS int* rank,
+                                          const DQMC_LDS double* rs, double* M, double* Z,
+                                          double* dst) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* stage = (double*)stage_lds;
+  DQMC_LDS double* red = stage_lds;                     // [NW] argmax keys
+  DQMC_LDS int* redi = (DQMC_LDS int*)(red + NW);       // [NW] argmax rows
+  DQMC_LDS double* prow = red + 2 * NW;                 // [QB] pivot row, panel part
+  DQMC_LDS double* Ap = prow + QB;                      // [QB][QB] A_P, then eliminated
+  DQMC_LDS double* Ai = Ap + QB * QB;                   // [QB][QB] A_P^{-1}
+  const int ldw = 2 * np;
+  double* Qp = scr;                                     // np x QB: M[r, K], zero on rows P
+  double* W = scr + (size_t)np * QB;                    // QB x ldw: A_P^{-1} [M[P, later] | Z[P, :]]
+  for (int k = tid; k < np; k += NT) rank[k] = -1;
+  __syncthreads();
+  double logabs = 0.0;
+  for (int k0 = 0; k0 < n; k0 += QB) {
+    const int nbk = min(QB, n - k0);
+    double p[RPT][QB], q[RPT][QB];
+    int rk[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const int r = tid + NT * m;
+      rk[m] = (r < n) ? rank[r] : 0;
+#pragma unroll
+      for (int c = 0; c < QB; ++c) {
+        const double v = (r < n && c < nbk) ? M[(size_t)r * np + k0 + c] : 0.0;
+        p[m][c] = v;
+        q[m][c] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      if (j < nbk) {
+        // pivot: largest |value| in column j among rows not yet pivoted (NaN counts as -0.5,
+        // so a row is always found); ties go to the lower row
+        double key = -1.0;
+        int idx = -1;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+          const int r = tid + NT * m;
+          if (r < n && rk[m] < 0) {
+            double v = fabs(p[m][j]);
+            v = (v == v) ? v : -0.5;
+            if (idx < 0 || v > key) { key = v; idx = r; }
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const double k2 = __shfl_xor(key, o);
+          const int i2 = __shfl_xor(idx, o);
+          if (i2 >= 0 && (idx < 0 || k2 > key || (k2 == key && i2 < idx))) { key = k2; idx = i2; }
+        }
+        if (lane == 0) { red[wave] = key; redi[wave] = idx; }
+        __syncthreads();
+        double bk = red[0];
+        int pr = redi[0];
+        for (int w = 1; w < NW; ++w) {
+          const double k2 = red[w];
+          const int i2 = redi[w];
+          if (i2 >= 0 && (pr < 0 || k2 > bk || (k2 == bk && i2 < pr))) { bk = k2; pr = i2; }
+        }
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+          if (pr == tid + NT * m) {
+#pragma unroll
+            for (int c = 0; c < QB; ++c) {
+              prow[c] = p[m][c];
+              Ap[j * QB + c] = q[m][c];
+            }
+            rank[pr] = k0 + j;
+            ordv[k0 + j] = pr;
+            rk[m] = k0 + j;
+          }
+        }
+        __syncthreads();
+        const double piv = prow[j];
+        logabs += log(fabs(piv));
+        const double ipiv = 1.0 / piv;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+          const int r = tid + NT * m;
+          if (r < n && rk[m] < 0) {
+            const double f = p[m][j] * ipiv;
+#pragma unroll
+            for (int c = j + 1; c < QB; ++c) p[m][c] -= f * prow[c];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // Qp = M[:, K] with the rows of P zeroed
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const int r = tid + NT * m;
+      if (r < np) {
+        const bool inP = (r < n) && rk[m] >= k0;
+#pragma unroll
+        for (int c = 0; c < QB; ++c) Qp[(size_t)r * QB + c] = inP ? 0.0 : q[m][c];
+      }
+    }
+    // A_P^{-1} by Gauss-Jordan without pivoting (identity on the padding of a short panel)
+    {
+      const int r = tid >> 4, c = tid & 15;   // NT = 256 = QB * QB entries
+      if (r >= nbk || c >= nbk) Ap[r * QB + c] = (r == c) ? 1.0 : 0.0;
+      Ai[r * QB + c] = (r == c) ? 1.0 : 0.0;
+      __syncthreads();
+      for (int s2 = 0; s2 < QB; ++s2) {
+        const double d = Ap[s2 * QB + s2];
+        const double fr = Ap[r * QB + s2];
+        const double as = Ap[s2 * QB + c], is = Ai[s2 * QB + c];
+        const double ar = Ap[r * QB + c], ir = Ai[r * QB + c];
+        __syncthreads();
+        if (r == s2) {
+          Ap[r * QB + c] = as / d;
+          Ai[r * QB + c] = is / d;
+        } else {
+          Ap[r * QB + c] = ar - fr * as / d;
+          Ai[r * QB + c] = ir - fr * is / d;
+        }
+        __syncthreads();
+      }
+    }
+    // W = A_P^{-1} [M[P, k0+QB .. n) | Z[P, :]]
+    const int nm = n - k0 - QB;
+    const int nmr = nm > 0 ? ((nm + 15) & ~15) : 0;
+    for (int col = tid; col < nmr + np; col += NT) {
+      double x[QB];
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        double v = 0.0;
+        if (b < nbk) {
+          const int row = ordv[k0 + b];
+          v = (col < nmr) ? M[(size_t)row * np + k0 + QB + col] : Z[(size_t)row * np + (col - nmr)];
+        }
+        x[b] = v;
+      }
+#pragma unroll
+      for (int a = 0; a < QB; ++a) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) s2 += Ai[a * QB + b] * x[b];
+        W[(size_t)a * ldw + col] = s2;
+      }
+    }
+    __syncthreads();
+    // rows not in P: x -= M[r, K] W;  rows in P: x = W (their Qp rows are zero)
+    if (nmr > 0) {
+      gemm_tiled<double>(stage, 1, np, nmr, QB, Qp, Qp, QB, 1, W, W, ldw, 1,
+                         [&](int, int i, int j, double v) {
+                           const int rr = rank[i];
+                           double* e = M + (size_t)i * np + k0 + QB + j;
+                           if (rr >= k0 && rr < k0 + QB) *e = W[(size_t)(rr - k0) * ldw + j];
+                           else *e -= v;
+                         });
+    }
+    gemm_tiled<double>(stage, 1, np, np, QB, Qp, Qp, QB, 1, W + nmr, W + nmr, ldw, 1,
+                       [&](int, int i, int j, double v) {
+                         const int rr = rank[i];
+                         double* e = Z + (size_t)i * np + j;
+                         if (rr >= k0 && rr < k0 + QB) *e = W[(size_t)(rr - k0) * ldw + nmr + j];
+                         else *e -= v;
+                       });
+    __syncthreads();
+  }
+  // solution row j sits in row ordv[j] of Z
+  for (int e = tid; e < np * np; e += NT) {
+    const int j = e / np, col = e - j * np;
+    double v = 0.0;
+    if (j < n) {
+      int row = ordv[j];
+      row = (row >= 0 && row < n) ? row : j;
+      v = Z[(size_t)row * np + col];
+      if (rs) v *= rs[j];
+    }
+    dst[e] = v;
+  }
+  __syncthreads();
+  return logabs;
+}
+
 // Fresh equal-time G^spin = [I + A B]^{-1} with A = UL DL TL (left, B(l,0)) and
 // B^T = UR DR TR (right, B(L,l)^T), by the two-sided split of the scales at 1:
 //   d = db ds, db = max(d,1), ds = min(d,1);
@@ -760,7 +1217,17 @@ __device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double
   });
   __syncthreads();
   // Z <- DRb^{-1} M^{-1} DLb^{-1} UL^T  (written into M's buffer)
-  double logm = wg_gauss_jordan(c, M, Z, M, iRb);
+  double logm;
+  if (c.qrv && c.stage && np <= QR_BLOCK_MAX_NP) {
+    DQMC_LDS double* stg = (DQMC_LDS double*)c.stage;
+    DQMC_LDS int* ordv = (DQMC_LDS int*)c.ordv;
+    DQMC_LDS int* rnk = (DQMC_LDS int*)c.rank;
+    const DQMC_LDS double* rsv = (const DQMC_LDS double*)iRb;
+    logm = (np <= NT) ? gj_blocked<1>(n, np, stg, c.qrv, ordv, rnk, rsv, M, Z, M)
+                      : gj_blocked<2>(n, np, stg, c.qrv, ordv, rnk, rsv, M, Z, M);
+  } else {
+    logm = wg_gauss_jordan(c, M, Z, M, iRb);
+  }
   // G = UR (DRb^{-1} M^{-1} DLb^{-1} UL^T)
   WT* G = c.G[spin];
   double dmax = 0.0;

@@ -35,7 +35,7 @@ class Model(ctypes.Structure):
                 ("U", ctypes.c_double), ("mu", ctypes.c_double), ("dtau", ctypes.c_double),
                 ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("delay_rank", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("qr_blocked", ctypes.c_int32)]
 
 
 OBS_DTYPE = np.dtype([("double_occ", "f8"), ("density", "f8"), ("kinetic", "f8"),
@@ -121,7 +121,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, delay_rank=0,
-               precision="fp64"):
+               precision="fp64", qr_blocked=False):
     """Build the C model struct; the returned object keeps the host hopping array alive."""
     T = np.ascontiguousarray(np.asarray(hopping, dtype=np.float64))
     if T.ndim != 2 or T.shape[0] != T.shape[1]:
@@ -133,6 +133,7 @@ def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, 
     m.n_slices, m.stab_every = int(n_slices), int(stab_every)
     m.refresh_every, m.delay_rank = int(refresh_every), int(delay_rank)
     m.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    m.qr_blocked = 1 if qr_blocked else 0
     m._keep = T
     return m
 

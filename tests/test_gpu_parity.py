@@ -172,8 +172,9 @@ def test_spin_structure_form_factors(dq):
 
 
 # ------------------------------------------------------------------ trajectories
-def _trajectory_check(dq, w, n, sweeps, delay_rank=0, first=0):
-    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank)
+def _trajectory_check(dq, w, n, sweeps, delay_rank=0, first=0, qr_blocked=False):
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank,
+                      qr_blocked=qr_blocked)
     b = dq.Batch(m, w.seeds(n, first), w.fields(n, first))
     _, oc = oracle_for(w, n, first)
     b.sweep(sweeps)
@@ -264,24 +265,43 @@ def test_trajectory_parity_square6x6_padded(dq):
     assert b.variant == 2
 
 
-def test_trajectory_parity_honeycomb6x6_generic(dq):
-    """N = 72 (padded to 80) runs in the generic kernels."""
-    b, _ = _trajectory_check(dq, di.WORKLOADS["honeycomb6x6_U3_b6"], 1, 1)
+@pytest.mark.parametrize("qr_blocked", [False, True])
+def test_trajectory_parity_honeycomb6x6_generic(dq, qr_blocked):
+    """N = 72 (padded to 80) runs in the generic kernels, with the column-pivoted or the blocked
+    stabilisation QR."""
+    b, _ = _trajectory_check(dq, di.WORKLOADS["honeycomb6x6_U3_b6"], 1, 1, qr_blocked=qr_blocked)
     assert b.variant in (0, 1)
 
 
-@pytest.mark.parametrize("name,cases", [
-    ("honeycomb12x12_U3_b6", [(0, 0), (30, 1), (60, 0)]),
-    ("square20x20_U8_b10", [(0, 0), (50, 1), (100, 0)]),
+@pytest.mark.parametrize("name,cases,qr_blocked", [
+    ("honeycomb12x12_U3_b6", [(0, 0), (30, 1), (60, 0)], False),
+    ("honeycomb12x12_U3_b6", [(0, 0), (30, 1), (60, 0)], True),
+    ("square20x20_U8_b10", [(0, 0), (50, 1), (100, 0)], False),
 ])
-def test_large_lattice_green_parity(dq, name, cases):
+def test_large_lattice_green_parity(dq, name, cases, qr_blocked):
     """Fresh G and one wrap at N = 288 and N = 400 to 1e-10 relative (longer wrap sequences at
-    these sizes differ between correct evaluations by more than that)."""
+    these sizes differ between correct evaluations by more than that); the blocked QR where it
+    applies (mildly graded products)."""
     w = di.WORKLOADS[name]
-    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, qr_blocked=qr_blocked)
     b = dq.Batch(m, w.seeds(1), w.fields(1))
     _, oc = oracle_for(w, 1)
     for sl, nw in cases:
         g = b.debug_green(sl, nw).cpu().numpy()
         ref = oc.debug_green(sl, nw)
         assert rel(g, ref) < 1e-10, (name, sl, nw, rel(g, ref))
+
+
+def test_qr_method_selection(dq):
+    """The autotuner keeps the column-pivoted QR where the blocked one departs from it (20x20,
+    U = 8, beta = 10: strongly graded products) and takes the blocked one at honeycomb 12x12,
+    U = 3, beta = 6."""
+    from paper_2106_00712_amd.autotune import Autotuner
+    at = Autotuner()
+    rec = {}
+    for name in ("honeycomb12x12_U3_b6", "square20x20_U8_b10"):
+        w = di.WORKLOADS[name]
+        rec[name] = at.qr_method(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(1), w.seeds(1),
+                                 w.stab_every)
+    assert rec["honeycomb12x12_U3_b6"]["qr_blocked"], rec
+    assert not rec["square20x20_U8_b10"]["qr_blocked"], rec
