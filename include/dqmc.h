@@ -64,7 +64,8 @@ typedef struct {
   int32_t stab_every;       /* FP64: slices between QR/UDT stabilisations (fresh G); >= 1 */
   int32_t refresh_every;    /* FP32_WRAP: slices between FP64 fresh-G refreshes (0 = stab_every).
                                The refresh points are also the stabilisation points. */
-  int32_t delay_rank;       /* k: sites per delayed-update block (0 = library default) */
+  int32_t delay_rank;       /* k: sites per delayed-update block (0 = library default: 16, 32 from
+                               N = 128 on) */
   int32_t precision;        /* dqmc_precision */
   int32_t qr_blocked;       /* 0: column-pivoted Householder QR in every stabilisation (default).
                                1: for 64 < N <= 512, blocked Householder QR with the columns

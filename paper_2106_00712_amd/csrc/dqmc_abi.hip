@@ -354,8 +354,9 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   L.J = (L.L + L.stab - 1) / L.stab;
   const size_t wts = m->precision == DQMC_FP32_WRAP ? sizeof(float) : sizeof(double);
   const size_t nn = (size_t)L.np * L.np;
-  // delay rank: multiple of 4; the small variant stores the panels in its work matrices
-  int kreq = m->delay_rank > 0 ? m->delay_rank : 16;
+  // delay rank: multiple of 4; the small variant stores the panels in its work matrices.  Default
+  // 16, and 32 from N = 128 on, where the flush (a pass over G in HBM per block) dominates
+  int kreq = m->delay_rank > 0 ? m->delay_rank : (L.n >= 128 ? 32 : 16);
   kreq = (kreq + 3) & ~3;
   const int lds_limit = query_device ? max_lds_per_block() : 160 * 1024;
   auto small_bytes = [&](int K) {

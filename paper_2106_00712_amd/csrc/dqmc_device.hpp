@@ -580,10 +580,27 @@ __device__ __forceinline__ void q_columns(int n, int np, const double* X, const 
 // zero padded), d_j = |R_jj| into dd (1 on padding), then X <- T' = D^{-1} S R P^T in original
 // column order, still column-major (zero padded): T'[a][col] = s_a R(a, col) / d_a when
 // rank[col] >= a.
+// Panel width of the blocked factorisations and the largest padded size they serve.
+constexpr int QB = 16;
+constexpr int QR_BLOCK_MAX_NP = 2 * NT;
+
+#ifndef DQMC_LDS
+#define DQMC_LDS __attribute__((address_space(3)))
+#endif
+
+__device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stage_lds, double* qrv,
+                                            const DQMC_LDS int* ordv, const DQMC_LDS double* vd,
+                                            const DQMC_LDS double* bt, const double* X, double* W,
+                                            double* Ud);
+
 template <typename WT>
-__device__ __forceinline__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* flags) {
+__device__ __forceinline__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, double* dd, int* flags,
+                                           double* wfree) {
   const int n = c.n, np = c.np, tid = threadIdx.x;
-  if (np <= 128) q_columns<2>(n, np, X, c.vd, c.bt, c.ordv, Ud);
+  if (wfree && c.qrv && c.stage && np <= QR_BLOCK_MAX_NP)
+    q_form_blocked(n, np, (DQMC_LDS double*)c.stage, c.qrv, (const DQMC_LDS int*)c.ordv,
+                   (const DQMC_LDS double*)c.vd, (const DQMC_LDS double*)c.bt, X, wfree, Ud);
+  else if (np <= 128) q_columns<2>(n, np, X, c.vd, c.bt, c.ordv, Ud);
   else if (np <= 256) q_columns<4>(n, np, X, c.vd, c.bt, c.ordv, Ud);
   else if (np <= 512) q_columns<8>(n, np, X, c.vd, c.bt, c.ordv, Ud);
   else if (np <= 1024) q_columns<16>(n, np, X, c.vd, c.bt, c.ordv, Ud);
@@ -628,12 +645,6 @@ __device__ __forceinline__ void udt_finish(Ctx<WT>& c, double* X, double* Ud, do
 // last panel back, both as MFMA products.  Outputs as wg_qrp + udt_finish: U = Q S into Ud
 // (row-major, zero padded), d = |diag R| into dd (1 on padding), and X <- T' = D^{-1} S R P^T
 // column-major in original column order (P the pre-pivot permutation).  A is a scratch matrix.
-constexpr int QB = 16;
-constexpr int QR_BLOCK_MAX_NP = 2 * NT;
-
-#ifndef DQMC_LDS
-#define DQMC_LDS __attribute__((address_space(3)))
-#endif
 
 // Not inlined: it has its own register budget inside the large generic sweep kernel, and one
 // instance per RPT serves both working precisions.  LDS arguments carry their address space.
@@ -864,6 +875,95 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
   __syncthreads();
 }
 
+// Explicit Q = H_0 H_1 ... H_{n-1} of the column-pivoted QR (wg_qrp: reflector j in column
+// ordv[j] of X below row j, its diagonal element in vd[j], beta_j in bt[j]) by compact-WY panels
+// of QB reflectors: V gathered clean into qrv, each panel's T from Y = V_p^T V_p (one small MFMA
+// product), then the backward accumulation Q <- (I - V_p T_p V_p^T) Q as in udt_blocked.  The
+// same Q as the column-by-column q_columns up to rounding.  W: a free np x np matrix.
+__device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stage_lds, double* qrv,
+                                            const DQMC_LDS int* ordv, const DQMC_LDS double* vd,
+                                            const DQMC_LDS double* bt, const double* X, double* W,
+                                            double* Ud) {
+  const int tid = threadIdx.x;
+  double* stage = (double*)stage_lds;
+  double* V = qrv;
+  double* Tg = qrv + (size_t)np * np;
+  for (int e = tid; e < np * np; e += NT) {
+    const int j = e / np, r = e - j * np;
+    double v = 0.0;
+    if (j < n) {
+      if (r == j) {
+        v = vd[j];
+      } else if (r > j && r < n) {
+        int col = ordv[j];
+        col = (col >= 0 && col < n) ? col : j;
+        v = X[(size_t)col * np + r];
+      }
+    }
+    V[e] = v;
+  }
+  __syncthreads();
+  const int npnl = (n + QB - 1) / QB;
+  DQMC_LDS double* Yl = stage_lds;
+  DQMC_LDS double* Tl = stage_lds + QB * QB;
+  for (int pnl = 0; pnl < npnl; ++pnl) {
+    const int k0 = pnl * QB, nbk = min(QB, n - k0);
+    const double* Vp = V + (size_t)k0 * np + k0;
+    double* Tp = Tg + (size_t)pnl * QB * QB;
+    gemm_tiled<double>(stage, 1, QB, QB, np - k0, Vp, Vp, np, 1, Vp, Vp, 1, np,
+                       [&](int, int i, int j, double v) { Tp[i * QB + j] = v; });
+    __syncthreads();
+    for (int e = tid; e < QB * QB; e += NT) Yl[e] = Tp[e];
+    __syncthreads();
+    if (tid == 0) {
+      for (int j = 0; j < QB; ++j) {
+        for (int i = 0; i < QB; ++i) Tl[i * QB + j] = 0.0;
+        if (j >= nbk) continue;
+        const double be = bt[k0 + j];
+        Tl[j * QB + j] = be;
+        for (int i = 0; i < j; ++i) {
+          double acc = 0.0;
+          for (int k = i; k < j; ++k) acc += Tl[i * QB + k] * Yl[k * QB + j];
+          Tl[i * QB + j] = -be * acc;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < QB * QB; e += NT) Tp[e] = Tl[e];
+    __syncthreads();
+  }
+  for (int e = tid; e < np * np; e += NT) {
+    const int r = e / np, col = e - r * np;
+    Ud[e] = (r == col && r < n) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int pnl = npnl - 1; pnl >= 0; --pnl) {
+    const int k0 = pnl * QB, w = np - k0;
+    const double* Vp = V + (size_t)k0 * np + k0;
+    double* Qb = Ud + (size_t)k0 * np + k0;
+    gemm_tiled<double>(stage, 1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
+                       [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
+    __syncthreads();
+    const double* T = Tg + (size_t)pnl * QB * QB;
+    for (int j = tid; j < w; j += NT) {
+      double t[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) t[q] = W[(size_t)q * np + j];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int b = q; b < QB; ++b) s2 += T[q * QB + b] * t[b];
+        W[(size_t)q * np + j] = s2;
+      }
+    }
+    __syncthreads();
+    gemm_tiled<double>(stage, 1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
+                       [&](int, int i, int j, double v) { Qb[(size_t)i * np + j] -= v; });
+    __syncthreads();
+  }
+}
+
 // Multiply a chunk of slice propagators onto (Us, ds, Ts) and re-factorise:
 //   left  (right == false): product B_{hi} ... B_{lo+1} U D, B_l = V_l expK;
 //   right (right == true):  product B_{lo+1}^T ... B_{hi}^T U D, B_l^T = expK^T V_l;
@@ -872,6 +972,8 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
 template <typename WT>
 __device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int lo, int hi, const double* Us,
                          const double* ds, const double* Ts, double* Ud, double* dd, double* Td) {
+  PhaseClock pc;
+  pc.start();
   const KArgs& a = *c.a;
   const int np = c.np, n = c.n;
   double* cur = c.w1;
@@ -914,6 +1016,7 @@ __device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int l
       double* t = cur; cur = nxt; nxt = t;
     }
   }
+  pc.stop(c.st, PH_CHUNK);
   if (a.qr_blocked && c.qrv && c.stage && np <= QR_BLOCK_MAX_NP) {
     DQMC_LDS double* stg = (DQMC_LDS double*)c.stage;
     DQMC_LDS double* nrm = (DQMC_LDS double*)c.nrm;
@@ -924,14 +1027,18 @@ __device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int l
     DQMC_LDS double* dtm = (DQMC_LDS double*)c.dtmp;
     if (np <= NT) udt_blocked<1>(n, np, stg, c.qrv, nrm, ordv, rnk, vdv, btv, dtm, cur, nxt, Ud, dd, &c.st->flags);
     else udt_blocked<2>(n, np, stg, c.qrv, nrm, ordv, rnk, vdv, btv, dtm, cur, nxt, Ud, dd, &c.st->flags);
+    pc.stop(c.st, PH_QR);
   } else {
     wg_qrp(c, cur);
-    udt_finish(c, cur, Ud, dd, &c.st->flags);
+    pc.stop(c.st, PH_QR);
+    udt_finish(c, cur, Ud, dd, &c.st->flags, nxt);
+    pc.stop(c.st, PH_QFORM);
   }
   // Td = T' Ts  (cur now holds T', column-major)
   ctx_gemm<double>(c, 1, np, np, np, cur, cur, 1, np, Ts, Ts, np, 1,
                   [&](int, int i, int j, double v) { Td[i * np + j] = v; });
   __syncthreads();
+  pc.stop(c.st, PH_TMUL);
 }
 
 // ------------------------------------------------------------------------------ fresh G
@@ -1193,6 +1300,8 @@ __device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double
                               const double* TL, const double* UR, const double* dR,
                               const double* TR, double* g64, double* logdet, bool drift) {
   const int np = c.np, n = c.n, tid = threadIdx.x;
+  PhaseClock pc;
+  pc.start();
   double* M = c.w1;
   double* Z = c.w2;
   // sr <- 1/DLb, sc <- 1/DRb for this call (slice scales are not live here)
@@ -1216,6 +1325,7 @@ __device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double
     M[i * np + j] += fmin(dL[i], 1.0) * v * fmin(dR[j], 1.0);
   });
   __syncthreads();
+  pc.stop(c.st, PH_FGEMM);
   // Z <- DRb^{-1} M^{-1} DLb^{-1} UL^T  (written into M's buffer)
   double logm;
   if (c.qrv && c.stage && np <= QR_BLOCK_MAX_NP) {
@@ -1228,6 +1338,7 @@ __device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double
   } else {
     logm = wg_gauss_jordan(c, M, Z, M, iRb);
   }
+  pc.stop(c.st, PH_GJ);
   // G = UR (DRb^{-1} M^{-1} DLb^{-1} UL^T)
   WT* G = c.G[spin];
   double dmax = 0.0;
@@ -1240,6 +1351,7 @@ __device__ __forceinline__ double fresh_green(Ctx<WT>& c, int spin, const double
     if (g64) g64[e] = v;
   });
   if (bad) atomicOr(&c.st->flags, FLAG_NONFINITE);
+  pc.stop(c.st, PH_GOUT);
   double ld = logm;
   {
     double part = 0.0;
