@@ -18,6 +18,11 @@
 
 #include "philox.hpp"
 
+// Pointer into LDS (address space 3), for arguments of functions that are not inlined.
+#ifndef DQMC_LDS
+#define DQMC_LDS __attribute__((address_space(3)))
+#endif
+
 namespace dqmc {
 
 constexpr int NT = 256;        // threads per workgroup (one chain)
@@ -540,6 +545,119 @@ __device__ __forceinline__ void wg_qrp(Ctx<WT>& c, double* X) {
   __syncthreads();
 }
 
+// wg_qrp for matrices in the workspace (np <= 64 CR): the same steps, pivots and per-lane
+// summation order (so the same bits), with each column's active part held in registers between
+// its dot product and its update instead of being read twice, and two columns per wavefront in
+// flight so that their memory latencies overlap.  vb: the pivot column (LDS, np doubles).
+template <int CR>
+__device__ __noinline__ void qrp_columns(int n, int np, double* X, DQMC_LDS double* nrm,
+                                         DQMC_LDS int* rank, DQMC_LDS int* ordv, DQMC_LDS double* vb,
+                                         DQMC_LDS double* vd, DQMC_LDS double* bt,
+                                         DQMC_LDS double* redv, DQMC_LDS int* redi) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = tid; k < n; k += NT) rank[k] = -1;
+  for (int col = wave; col < n; col += NW) {
+    double s = 0;
+    for (int r = lane; r < n; r += 64) { const double x = X[(size_t)col * np + r]; s += x * x; }
+    s = wave_sum_dpp(s);
+    if (lane == 0) nrm[col] = s;
+  }
+  double alpha_prev = 0, v0_prev = 0, beta_prev = 0;
+  int p_prev = -1;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0 && p_prev >= 0) {
+      X[(size_t)p_prev * np + (j - 1)] = alpha_prev;
+      vd[j - 1] = v0_prev;
+      bt[j - 1] = beta_prev;
+    }
+    // pivot: the remaining column of largest norm, ties to the lower index
+    double key = -1.0;
+    int idx = -1;
+    for (int k = tid; k < n; k += NT) {
+      if (rank[k] < 0) {
+        const double v = nrm[k];
+        if (idx < 0 || v > key) { key = v; idx = k; }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double k2 = __shfl_xor(key, o);
+      const int i2 = __shfl_xor(idx, o);
+      if (i2 >= 0 && (idx < 0 || k2 > key || (k2 == key && i2 < idx))) { key = k2; idx = i2; }
+    }
+    if (lane == 0) { redv[wave] = key; redi[wave] = idx; }
+    __syncthreads();
+    int p = redi[0];
+    {
+      double bk = redv[0];
+      for (int w = 1; w < NW; ++w) {
+        const double k2 = redv[w];
+        const int i2 = redi[w];
+        if (i2 >= 0 && (p < 0 || k2 > bk || (k2 == bk && i2 < p))) { bk = k2; p = i2; }
+      }
+    }
+    p = (p >= 0 && p < n) ? p : j;
+    const double* xp = X + (size_t)p * np;
+    const double xj = xp[j];
+    const double nx = sqrt(nrm[p]);
+    const double alpha = (xj >= 0.0) ? -nx : nx;
+    const double beta = (nx > 0.0) ? 1.0 / (alpha * (alpha - xj)) : 0.0;
+    const double v0 = xj - alpha;
+    for (int r = j + tid; r < n; r += NT) vb[r] = (r == j) ? v0 : xp[r];
+    if (tid == 0) { rank[p] = j; ordv[j] = p; }
+    __syncthreads();
+    for (int col = wave; col < n; col += 2 * NW) {
+      const int cb = col + NW;
+      const bool ua = (col != p) && rank[col] < 0;
+      const bool ub = (cb < n) && (cb != p) && rank[cb] < 0;
+      if (!ua && !ub) continue;
+      double* xa = X + (size_t)col * np;
+      double* xb = X + (size_t)(ub ? cb : col) * np;
+      double ra[CR], rb[CR];
+#pragma unroll
+      for (int t = 0; t < CR; ++t) {
+        const int r = j + lane + 64 * t;
+        ra[t] = (ua && r < n) ? xa[r] : 0.0;
+        rb[t] = (ub && r < n) ? xb[r] : 0.0;
+      }
+      double wa = 0, wb = 0;
+#pragma unroll
+      for (int t = 0; t < CR; ++t) {
+        const int r = j + lane + 64 * t;
+        if (r < n) {
+          wa += vb[r] * ra[t];
+          wb += vb[r] * rb[t];
+        }
+      }
+      if (ua) wa = wave_sum_dpp(wa) * beta;
+      if (ub) wb = wave_sum_dpp(wb) * beta;
+      double sa = 0, sb = 0;
+#pragma unroll
+      for (int t = 0; t < CR; ++t) {
+        const int r = j + lane + 64 * t;
+        if (r < n) {
+          const double v = vb[r];
+          const double ya = ra[t] - wa * v;
+          const double yb = rb[t] - wb * v;
+          if (ua) xa[r] = ya;
+          if (ub) xb[r] = yb;
+          if (r > j) { sa += ya * ya; sb += yb * yb; }
+        }
+      }
+      if (ua) { sa = wave_sum_dpp(sa); if (lane == 0) nrm[col] = sa; }
+      if (ub) { sb = wave_sum_dpp(sb); if (lane == 0) nrm[cb] = sb; }
+    }
+    alpha_prev = alpha; v0_prev = v0; beta_prev = beta; p_prev = p;
+    __syncthreads();
+  }
+  if (tid == 0 && p_prev >= 0) {
+    X[(size_t)p_prev * np + (n - 1)] = alpha_prev;
+    vd[n - 1] = v0_prev;
+    bt[n - 1] = beta_prev;
+  }
+  __syncthreads();
+}
+
 // Column jj of Q = H_0 H_1 ... H_jj e_jj (later reflectors do not touch e_jj), one wavefront per
 // column with the column in registers (element r = lane + 64 t), written to Ud (row-major).
 template <int CR>
@@ -584,9 +702,6 @@ __device__ __forceinline__ void q_columns(int n, int np, const double* X, const 
 constexpr int QB = 16;
 constexpr int QR_BLOCK_MAX_NP = 2 * NT;
 
-#ifndef DQMC_LDS
-#define DQMC_LDS __attribute__((address_space(3)))
-#endif
 
 __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stage_lds, double* qrv,
                                             const DQMC_LDS int* ordv, const DQMC_LDS double* vd,
@@ -1029,7 +1144,21 @@ __device__ __forceinline__ void udt_push(Ctx<WT>& c, int spin, bool right, int l
     else udt_blocked<2>(n, np, stg, c.qrv, nrm, ordv, rnk, vdv, btv, dtm, cur, nxt, Ud, dd, &c.st->flags);
     pc.stop(c.st, PH_QR);
   } else {
-    wg_qrp(c, cur);
+    if (c.stage && np <= QR_BLOCK_MAX_NP) {
+      DQMC_LDS double* nrm = (DQMC_LDS double*)c.nrm;
+      DQMC_LDS int* rnk = (DQMC_LDS int*)c.rank;
+      DQMC_LDS int* ordv = (DQMC_LDS int*)c.ordv;
+      DQMC_LDS double* vb = (DQMC_LDS double*)c.sc;
+      DQMC_LDS double* vdv = (DQMC_LDS double*)c.vd;
+      DQMC_LDS double* btv = (DQMC_LDS double*)c.bt;
+      DQMC_LDS double* rv = (DQMC_LDS double*)c.red.v;
+      DQMC_LDS int* ri = (DQMC_LDS int*)c.red.i;
+      if (np <= 128) qrp_columns<2>(n, np, cur, nrm, rnk, ordv, vb, vdv, btv, rv, ri);
+      else if (np <= 256) qrp_columns<4>(n, np, cur, nrm, rnk, ordv, vb, vdv, btv, rv, ri);
+      else qrp_columns<8>(n, np, cur, nrm, rnk, ordv, vb, vdv, btv, rv, ri);
+    } else {
+      wg_qrp(c, cur);
+    }
     pc.stop(c.st, PH_QR);
     udt_finish(c, cur, Ud, dd, &c.st->flags, nxt);
     pc.stop(c.st, PH_QFORM);
