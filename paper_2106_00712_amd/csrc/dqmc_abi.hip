@@ -314,6 +314,7 @@ struct Layout {
       c_slots, c_err, c_end;
   // per chain
   size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, o_qrv, stride;
+  int KT;   // accumulated delayed-update rank (workspace variant), 0 otherwise
 };
 
 int max_lds_per_block() {
@@ -423,12 +424,19 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   L.o_Gw = ctake(2 * nn * 8);   // working G of the global variant / parked G of the fast path
   if (!L.small) {
     L.o_work = ctake(2 * nn * 8);
-    L.o_xy = ctake(4 * (size_t)L.np * L.K * wts);
+    // two-level delayed updates from N = 128 on (below, the correction products cost more than
+    // the flushes they save): panels XA, YA of rank KT = 4K for both spins, the corrected columns
+    // and rows of one block, and the gathered panel rows and columns
+    L.KT = (L.n >= 128) ? 4 * L.K : 0;
+    const size_t K16 = (L.K + 15) & ~15;
+    L.o_xy = L.KT ? ctake((4 * (size_t)L.np * L.KT + 4 * (size_t)L.np * K16 + 4 * (size_t)L.KT * K16) * wts)
+                  : ctake(4 * (size_t)L.np * L.K * wts);
     // blocked factorisations (np <= QR_BLOCK_MAX_NP): QR reflectors (np x np) and one QB x QB
     // T per panel; the Gauss-Jordan solve reuses the first 3 QB np doubles
     L.o_qrv = (L.np <= QR_BLOCK_MAX_NP) ? ctake((nn + (size_t)QB * L.np) * 8) : 0;
   } else {
     L.o_work = L.o_xy = L.o_qrv = 0;
+    L.KT = 0;
   }
   L.stride = align256(co);
   *out = L;
@@ -438,6 +446,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
 void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KArgs* a) {
   std::memset(a, 0, sizeof(*a));
   a->n = L.n; a->np = L.np; a->L = L.L; a->stab = L.stab; a->J = L.J; a->K = L.K;
+  a->KT = L.KT;
   a->n_chains = n_chains;
   const double nu = std::acosh(std::exp(0.5 * m->U * m->dtau));
   a->nu = nu;

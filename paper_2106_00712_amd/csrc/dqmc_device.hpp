@@ -58,6 +58,7 @@ struct PhaseClock {
 // Everything a kernel launch needs (passed by value).
 struct KArgs {
   int n, np, L, stab, J, K, n_chains, op, slice, n_wraps, n_sweeps, gen_fields;
+  int KT;               // accumulated delayed-update rank of the N > 64 workspace kernels (0: none)
   double nu, drift_limit;
   double ev[2];     // e^{+nu}, e^{-nu}
   double dup[2];    // Delta^up(s)   = e^{-2 nu s} - 1 for s = -1 (index 0), s = +1 (index 1)
@@ -1674,6 +1675,195 @@ __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldru
   }
 }
 
+// Delayed updates in two levels for the matrices in the workspace: blocks of K sites are decided
+// as in metropolis_slice, but their accepted flips are appended to accumulated panels XA
+// (np x KT, column-major) and YA (KT x np, row-major) instead of entering G at once; the true
+// Green's function is G + XA YA.  A block reads its own entries, and the columns and rows of its
+// accepted sites, through that correction (small MFMA products), so the decisions and the new
+// Sherman-Morrison vectors are those of the one-level scheme; G takes the accumulated rank in one
+// product when the panels are full and at the end of the slice.  This replaces one pass over G
+// in HBM per block by one per KT / K blocks.
+template <typename WT>
+__device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldrun) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np, K = c.K, KT = a.KT, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K2 = K * K, K16 = (K + 15) & ~15;
+  int8_t* fl = c.f + (size_t)(l - 1) * np;
+  const uint64_t seed = c.st->seed;
+  const int64_t sweep = c.st->sweeps_done;
+  int64_t acc_total = 0;
+  const size_t pn = (size_t)np * KT;
+  WT* XA[2] = {c.xy, c.xy + pn};
+  WT* YA[2] = {c.xy + 2 * pn, c.xy + 3 * pn};
+  WT* base = c.xy + 4 * pn;
+  WT* Cc[2] = {base, base + (size_t)np * K16};                       // np x K16, column-major
+  WT* Rw[2] = {base + 2 * (size_t)np * K16, base + 3 * (size_t)np * K16};   // K16 x np, row-major
+  base += 4 * (size_t)np * K16;
+  WT* Ys[2] = {base, base + (size_t)KT * K16};                       // KT x K16: YA[u][a_t]
+  WT* Xs[2] = {base + 2 * (size_t)KT * K16, base + 3 * (size_t)KT * K16};   // K16 x KT: XA[a_t][u]
+  int mA = 0;
+  PhaseClock clk;
+  clk.start();
+  for (int i0 = 0; i0 < n; i0 += K) {
+    const int kb = min(K, n - i0);
+    // ---- the block of the true G
+    if (mA > 0) {
+      const int kr = (kb + 15) & ~15;
+      wg_gemm<WT>(2, kr, kr, mA, XA[0] + i0, XA[1] + i0, 1, np, YA[0] + i0, YA[1] + i0, np, 1,
+                  [&](int b, int i, int j, WT v) {
+                    if (i < kb && j < kb)
+                      c.gb[b * K2 + i * K + j] = (double)c.G[b][(i0 + i) * np + i0 + j] + (double)v;
+                  });
+      __syncthreads();
+    }
+    if (wave == 0) {
+      if (mA == 0) {
+        for (int e = lane; e < kb * kb; e += 64) {
+          int r = e / kb, cc = e - r * kb;
+          c.gb[r * K + cc] = (double)c.G[0][(i0 + r) * np + i0 + cc];
+          c.gb[K2 + r * K + cc] = (double)c.G[1][(i0 + r) * np + i0 + cc];
+        }
+      }
+      if (lane < kb) {
+        c.ublk[lane] = accept_uniform(seed, sweep, l - 1, i0 + lane);
+        c.sblk[lane] = fl[i0 + lane];
+      }
+      wave_sync();
+      int m = 0;
+      double ldu = 0.0, ldd = 0.0;
+      int flg = 0;
+      int64_t ties = 0;
+      for (int ii = 0; ii < kb; ++ii) {
+        const int s = c.sblk[ii];
+        const double u = c.ublk[ii];
+        const double gu = c.gb[ii * K + ii], gd = c.gb[K2 + ii * K + ii];
+        const double du = a.dup[s > 0], dd = a.ddn[s > 0];
+        const double ru = 1.0 + du * (1.0 - gu), rd = 1.0 + dd * (1.0 - gd);
+        const double R = ru * rd;
+        bool ok = true;
+        if (!(fabs(R) < 1e300)) { flg |= FLAG_NONFINITE; ok = false; }
+        else if (R < 0.0) { flg |= FLAG_NEGATIVE; ok = false; }
+        if (ok && fabs(u - R) < 1e-9) ++ties;
+        if (ok && u < R) {
+          const double cu = du / ru, cd = dd / rd;
+          if (lane < kb) {
+            const int r = lane;
+            c.xb[r * K + m] = -cu * c.gb[r * K + ii];
+            c.xb[K2 + r * K + m] = -cd * c.gb[K2 + r * K + ii];
+            c.yb[m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[ii * K + r];
+            c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
+          }
+          wave_sync();
+          for (int e = lane; e < kb * kb; e += 64) {
+            int r = e / kb, cc = e - r * kb;
+            c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
+            c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
+          }
+          if (lane == 0) {
+            c.site[m] = ii;
+            c.cfu[m] = cu;
+            c.cfd[m] = cd;
+            fl[i0 + ii] = (int8_t)(-s);
+          }
+          ldu += log(fabs(ru));
+          ldd += log(fabs(rd));
+          ++m;
+          wave_sync();
+        }
+      }
+      if (lane == 0) {
+        c.cnt[0] = m;
+        ldrun[0] += ldu;
+        ldrun[1] += ldd;
+        if (flg) atomicOr(&c.st->flags, flg);
+        c.st->near_ties += ties;
+      }
+    }
+    __syncthreads();
+    clk.stop(c.st, PH_DECIDE);
+    const int m = c.cnt[0];
+    acc_total += m;
+    if (m > 0) {
+      const int mp = (m + 3) & ~3;
+      // ---- columns and rows of the true G at the accepted sites
+      if (mA > 0) {
+        const int mr = (mp + 15) & ~15;
+        for (int e = tid; e < 2 * mA * mr; e += NT) {
+          const int b = e / (mA * mr), rem = e - b * (mA * mr), u = rem / mr, t = rem - u * mr;
+          const int col = (t < m) ? i0 + c.site[t] : -1;
+          Ys[b][u * K16 + t] = (col >= 0) ? YA[b][(size_t)u * np + col] : (WT)0;
+          Xs[b][t * KT + u] = (col >= 0) ? XA[b][(size_t)u * np + col] : (WT)0;
+        }
+        __syncthreads();
+        ctx_gemm<WT>(c, 2, np, mr, mA, XA[0], XA[1], 1, np, Ys[0], Ys[1], K16, 1,
+                     [&](int b, int i, int j, WT v) {
+                       if (j < m)
+                         Cc[b][(size_t)j * np + i] =
+                             (WT)(((i < n) ? (double)c.G[b][i * np + i0 + c.site[j]] : 0.0) + (double)v);
+                     });
+        ctx_gemm<WT>(c, 2, mr, np, mA, Xs[0], Xs[1], KT, 1, YA[0], YA[1], np, 1,
+                     [&](int b, int i, int j, WT v) {
+                       if (i < m)
+                         Rw[b][(size_t)i * np + j] =
+                             (WT)(((j < n) ? (double)c.G[b][(i0 + c.site[i]) * np + j] : 0.0) + (double)v);
+                     });
+        __syncthreads();
+      }
+      // ---- the block's Sherman-Morrison vectors, appended to the panels at mA .. mA + mp
+      for (int e = tid; e < 4 * np; e += NT) {
+        const int kind = e / (2 * np);          // 0: X rows, 1: Y columns
+        const int sp = (e / np) & 1;
+        const int r = e - (e / np) * np;        // row (X) or column (Y)
+        const WT* G0 = c.G[sp];
+        const double* cf = sp ? c.cfd : c.cfu;
+        const double* xbs = c.xb + sp * K2;
+        const double* ybs = c.yb + sp * K2;
+        double tmp[64];
+        if (kind == 0) {
+          WT* X = XA[sp] + (size_t)mA * np;
+          for (int t = 0; t < m; ++t) {
+            const int jt = c.site[t];
+            double acc = 0.0;
+            if (r < n) acc = mA ? (double)Cc[sp][(size_t)t * np + r] : (double)G0[r * np + i0 + jt];
+            for (int t2 = 0; t2 < t; ++t2) acc += tmp[t2] * ybs[t2 * K + jt];
+            tmp[t] = -cf[t] * acc;
+            X[(size_t)t * np + r] = (WT)tmp[t];
+          }
+          for (int t = m; t < mp; ++t) X[(size_t)t * np + r] = (WT)0;
+        } else {
+          WT* Y = YA[sp] + (size_t)mA * np;
+          for (int t = 0; t < m; ++t) {
+            const int jt = c.site[t];
+            double g = 0.0;
+            if (r < n) g = mA ? (double)Rw[sp][(size_t)t * np + r] : (double)G0[(i0 + jt) * np + r];
+            double acc = ((r == i0 + jt) ? 1.0 : 0.0) - g;
+            for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * K + t2] * tmp[t2];
+            if (r >= n) acc = 0.0;
+            tmp[t] = acc;
+            Y[(size_t)t * np + r] = (WT)acc;
+          }
+          for (int t = m; t < mp; ++t) Y[(size_t)t * np + r] = (WT)0;
+        }
+      }
+      __syncthreads();
+      clk.stop(c.st, PH_PANEL);
+      mA += mp;
+    }
+    // ---- G += XA YA when the next block might not fit, and at the end of the slice
+    if (mA > 0 && (i0 + K >= n || mA + K > KT)) {
+      ctx_gemm<WT>(c, 2, np, np, mA, XA[0], XA[1], 1, np, YA[0], YA[1], np, 1,
+                   [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
+      __syncthreads();
+      clk.stop(c.st, PH_FLUSH);
+      mA = 0;
+    }
+  }
+  if (tid == 0) {
+    c.st->attempted += n;
+    c.st->accepted += acc_total;
+  }
+}
+
 // ------------------------------------------------------------------------------ stacks
 // Pointers into the right stack (entry j: UDT of B(L, j*stab)^T) and the left factors.
 template <typename WT>
@@ -1774,7 +1964,8 @@ __device__ __forceinline__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
       clk.start();
       wrap_both(c, l);
       clk.stop(c.st, PH_WRAP);
-      metropolis_slice(c, l, ldrun);
+      if (c.stage && a.KT > 0) metropolis_slice2(c, l, ldrun);
+      else metropolis_slice(c, l, ldrun);
       __syncthreads();
       clk.start();
       if (l % c.stab == 0 || l == L) {

@@ -252,6 +252,15 @@ def test_rejects_small_workspace(dq):
 # ------------------------------------------------------------------ other sizes
 SQUARE6 = di.Workload("square6x6_U4_b2", 7, "square", 6, 4.0, 2.0, 0.1, 2, 2, 10)
 SQUARE2 = di.Workload("square2x2_U4_b2", 8, "square", 2, 4.0, 2.0, 0.1, 2, 5, 5)
+SQUARE12 = di.Workload("square12x12_U4_b2", 9, "square", 12, 4.0, 2.0, 0.1, 1, 1, 10)
+
+
+@pytest.mark.parametrize("qr_blocked", [False, True])
+def test_trajectory_parity_square12x12_two_level_delay(dq, qr_blocked):
+    """N = 144: delay rank 32 with the accumulated panels (rank up to 128) flushed into G only
+    when full and at the end of each slice (4.5 blocks per slice, a partial last block)."""
+    b, _ = _trajectory_check(dq, SQUARE12, 1, 2, qr_blocked=qr_blocked)
+    assert b.delay_rank == 32
 
 
 def test_trajectory_parity_square2x2(dq):
