@@ -7,10 +7,10 @@ with the HIP path (paper_2106_00712_amd) and neither side imports the other; bot
 seeded inputs from dqmc_inputs, which holds none of the method's arithmetic.
 """
 from .dqmc_oracle import (Model, OracleChains, hs_nu, kinetic_propagators, slice_B, slice_Binv,
-                          udt, udt_product, green_two_sided, measure_from_green,
+                          udt, udt_exact_pivot, udt_product, green_two_sided, measure_from_green,
                           spin_structure)
 from .philox import philox4x64_10, accept_uniform, to_unit
 
-__all__ = ["Model", "OracleChains", "hs_nu", "kinetic_propagators", "slice_B", "slice_Binv", "udt",
+__all__ = ["Model", "OracleChains", "hs_nu", "kinetic_propagators", "slice_B", "slice_Binv", "udt", "udt_exact_pivot",
            "udt_product", "green_two_sided", "measure_from_green", "spin_structure", "philox4x64_10",
            "accept_uniform", "to_unit"]

@@ -81,18 +81,60 @@ def udt(X: np.ndarray):
     return U, d, T
 
 
-def udt_product(factors: List[np.ndarray], chunk: int, n: int):
+def udt_exact_pivot(X: np.ndarray):
+    """As udt, with the pivot of every step chosen from the column norms recomputed exactly on
+    the partly reduced matrix (LAPACK's pivoted QR downdates them instead).  Both rules take the
+    largest remaining norm; they part only where remaining norms tie to rounding, and then give
+    different, equally valid factorisations.  Plain Householder steps:
+      column j: x = A[j:, pivot], alpha = -sign(x_0) |x|, v = x - alpha e_0,
+      beta = 1 / (alpha (alpha - x_0)), A[j:, j:] <- (I - beta v v^T) A[j:, j:];
+    Q = H_0 ... H_{n-1} applied to I from the last reflector back."""
+    A = np.array(X, dtype=np.float64, copy=True)
+    n = A.shape[1]
+    piv = np.arange(n)
+    refl = []
+    for j in range(n):
+        nrm = np.sum(A[j:, j:] ** 2, axis=0)
+        p = j + int(np.argmax(nrm))
+        A[:, [j, p]] = A[:, [p, j]]
+        piv[[j, p]] = piv[[p, j]]
+        x = A[j:, j].copy()
+        nx = float(np.sqrt(np.sum(x * x)))
+        alpha = -nx if x[0] >= 0.0 else nx
+        v = x.copy()
+        v[0] -= alpha
+        beta = 1.0 / (alpha * (alpha - x[0])) if nx > 0.0 else 0.0
+        A[j:, j:] -= beta * np.outer(v, v @ A[j:, j:])
+        refl.append((v, beta))
+    R = np.triu(A)
+    Q = np.eye(A.shape[0])
+    for j in range(n - 1, -1, -1):
+        v, beta = refl[j]
+        Q[j:, :] -= beta * np.outer(v, v @ Q[j:, :])
+    r = np.diag(R)
+    sgn = np.where(r < 0.0, -1.0, 1.0)
+    d = np.abs(r)
+    U = Q * sgn[None, :]
+    Rn = (sgn[:, None] * R) / d[:, None]
+    T = np.empty_like(Rn)
+    T[:, piv] = Rn
+    return U, d, T
+
+
+def udt_product(factors: List[np.ndarray], chunk: int, n: int, factorise=None):
     """UDT of factors[-1] @ ... @ factors[0] (n x n), re-factorised after every `chunk` factors.
 
     Each chunk is multiplied onto U Diag(d) and factorised again; the new T' multiplies the
     accumulated T from the left.  The scales of the product live only in d.  No factors: I.
+    `factorise` is udt (LAPACK's pivoted QR) unless another UDT routine is given.
     """
+    factorise = factorise or udt
     U, d, T = np.eye(n), np.ones(n), np.eye(n)
     for start in range(0, len(factors), chunk):
         X = U * d[None, :]
         for F in factors[start:start + chunk]:
             X = F @ X
-        U, d, Tn = udt(X)
+        U, d, Tn = factorise(X)
         T = Tn @ T
     return U, d, T
 
@@ -126,6 +168,7 @@ class Model:
     n_slices: int
     stab_every: int
     mu: float = 0.0
+    exact_pivot: bool = False   # UDT by udt_exact_pivot instead of LAPACK's pivoted QR
 
     def __post_init__(self):
         self.T = np.asarray(self.T, dtype=np.float64)
@@ -146,10 +189,11 @@ class Model:
         = B_{l+1}^T ... B_{L_tau}^T from slice L_tau downwards, each in chunks of stab_every.
         """
         Lt = self.n_slices
+        fac = udt_exact_pivot if self.exact_pivot else udt
         left = udt_product([self.B(fields[k - 1], sigma) for k in range(1, l + 1)],
-                           self.stab_every, self.N)
+                           self.stab_every, self.N, fac)
         right_t = udt_product([self.B(fields[k - 1], sigma).T for k in range(Lt, l, -1)],
-                              self.stab_every, self.N)
+                              self.stab_every, self.N, fac)
         return green_two_sided(left, right_t)
 
     def wrap(self, G, s_l, sigma):

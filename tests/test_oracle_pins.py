@@ -355,3 +355,45 @@ def test_spin_structure_free_fermions():
     f = 1.0 / (1.0 + np.exp(2.0 * lam))
     ref = float(np.sum(f * (1 - f))) / (2 * 16)
     assert math.isclose(spin_structure(G, G, np.ones(16)), ref, rel_tol=1e-12)
+
+
+# ------------------------------------------------------------------ exact-norm pivoting
+def test_udt_exact_pivot_is_a_pivoted_udt():
+    """X = U D T with U orthogonal and, column-pivoted QR's defining property, every entry of
+    T' = D^-1 S R at most 1 in size (|R_jj| >= |R_ij|); on a graded random matrix."""
+    from oracle import udt_exact_pivot
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((40, 40)) @ np.diag(np.exp(rng.uniform(-25, 25, 40)))
+    U, d, T = udt_exact_pivot(X)
+    assert np.max(np.abs(U.T @ U - np.eye(40))) < 1e-13
+    rec = (U * d[None, :]) @ T
+    assert np.max(np.abs(rec - X) / np.abs(X).max(axis=0)[None, :]) < 1e-13
+    assert np.max(np.abs(T)) <= 1.0 + 1e-12
+    assert np.all(d[:-1] >= d[1:] * (1 - 1e-12))     # the pivoted diagonal does not increase
+
+
+def test_udt_exact_pivot_matches_lapack_when_norms_separate():
+    """With well separated column norms both pivot rules take the same columns: the same U, d, T
+    as LAPACK's pivoted QR to rounding."""
+    from oracle import udt, udt_exact_pivot
+    rng = np.random.default_rng(12)
+    # a well-conditioned matrix with its columns scaled a factor ~3 apart, in shuffled order
+    B = np.eye(30) + 0.1 * rng.standard_normal((30, 30))
+    X = (B * (10.0 ** (-np.arange(30) / 2.0))[None, :])[:, rng.permutation(30)]
+    a, b = udt(X), udt_exact_pivot(X)
+    for u, v in zip(a, b):
+        assert np.max(np.abs(u - v)) < 1e-10 * max(1.0, np.max(np.abs(u)))
+
+
+def test_exact_pivot_green_matches_lapack_green():
+    """Fresh G by the exact-norm variant equals the LAPACK-pivoted oracle on a mildly graded
+    workload (honeycomb 6x6, U = 3, beta = 6) to 1e-11."""
+    from oracle import Model
+    w = di.WORKLOADS["honeycomb6x6_U3_b6"]
+    f = w.fields(1)[0]
+    a = Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    b = Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, exact_pivot=True)
+    for l in (0, 30):
+        ga, la = a.green(f, l, +1)
+        gb, lb = b.green(f, l, +1)
+        assert np.max(np.abs(ga - gb)) < 1e-11 and abs(la - lb) < 1e-9
