@@ -217,28 +217,40 @@ def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
     eps = di.staggered_sign(w.lattice, w.L)
     m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
     b = dqmc.Batch(m, w.seeds(n_chains, seed_first))
+    from paper_2106_00712_amd import analysis
     t0 = time.perf_counter()
-    for k in range(therm):
+    conv_pts = set(range(1, 21)) | set(range(25, therm + 1, 25))
+    conv = {"sweeps": [], "E_k": [], "E_k_se": [], "S_Gamma_moments": [], "S_Gamma_moments_se": []}
+    for k in range(1, therm + 1):
         b.sweep(1)
-        if (k + 1) % 50 == 0:
-            torch.cuda.synchronize()
-            print(f"physics: thermalised {k + 1}/{therm} sweeps", file=sys.stderr, flush=True)
+        if k in conv_pts:     # the paper's Fig. 3 form: chain averages after each sweep
+            o = b.measure()
+            sm = 4.0 * b.spin_structure(eps).cpu().numpy()
+            conv["sweeps"].append(k)
+            for key, v in (("E_k", o["kinetic"]), ("S_Gamma_moments", sm)):
+                mu, se = analysis.mean_and_error(v)
+                conv[key].append(mu)
+                conv[key + "_se"].append(se)
+        if k % 50 == 0:
+            print(f"physics: thermalised {k}/{therm} sweeps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_therm = time.perf_counter() - t0
-    sums = torch.zeros((4, n_chains), dtype=torch.float64, device=b.device)
+    ser = np.zeros((4, n_chains, meas))
     for k in range(meas):
         b.sweep(1)
         o = b.measure()
-        s = b.spin_structure(eps)
-        sums[0] += torch.from_numpy(o["kinetic"].copy()).to(b.device)
-        sums[1] += s
-        sums[2] += torch.from_numpy(o["double_occ"].copy()).to(b.device)
-        sums[3] += torch.from_numpy(o["density"].copy()).to(b.device)
+        ser[0, :, k] = o["kinetic"]
+        ser[1, :, k] = b.spin_structure(eps).cpu().numpy()
+        ser[2, :, k] = o["double_occ"]
+        ser[3, :, k] = o["density"]
         if (k + 1) % 50 == 0:
             print(f"physics: measured {k + 1}/{meas} sweeps", file=sys.stderr, flush=True)
     o = b.measure()
     wall = time.perf_counter() - t0
-    per_chain = (sums / meas).cpu().numpy()
+    per_chain = ser.mean(axis=2)
+    t_max = min(100, meas // 4)
+    a_s = analysis.autocorrelation(ser[1], t_max)
+    a_e = analysis.autocorrelation(ser[0], t_max)
 
     def stat(v):
         return float(v.mean()), float(v.std(ddof=1) / np.sqrt(len(v)))
@@ -254,7 +266,10 @@ def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
            "acceptance": float(o["accepted"].sum() / max(1, o["attempted"].sum())),
            "flags": int(np.bitwise_or.reduce(o["flags"])), "max_drift": float(o["max_drift"].max()),
            "near_ties": int(o["near_ties"].sum()), "seconds_thermalise": t_therm, "seconds_total": wall,
-           "paper_good_dqmc": PAPER_TABLE2}
+           "paper_good_dqmc": PAPER_TABLE2, "convergence": conv,
+           "autocorr_S_Gamma": {str(t): float(a_s[t]) for t in (1, 2, 5, 10, 20, 50, 100) if t < len(a_s)},
+           "autocorr_E_k": {str(t): float(a_e[t]) for t in (1, 2, 5, 10, 20, 50, 100) if t < len(a_e)},
+           "tau_int_S_Gamma": analysis.integrated_time(a_s), "tau_int_E_k": analysis.integrated_time(a_e)}
     for key, (mu, se) in (("E_k", ek), ("S_Gamma_1_over_N", s_n), ("S_Gamma_1_over_L2", s_l2),
                           ("S_Gamma_moments_1_over_N", s_m)):
         pm, pe = PAPER_TABLE2["E_k" if key == "E_k" else "S_Gamma"]
@@ -286,6 +301,7 @@ def run_ising(L: int, T: float, n_chains: int, therm: int, meas: int, ac_len: in
     conv = b.sweep(conv_len, measure=False, series=True)
     am = np.abs(conv[:, :, 0].double().cpu().numpy()) / n
     curve, curve_se = analysis.convergence_curve(am)
+    del conv
     b.sweep(max(0, therm - conv_len), measure=False)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -302,6 +318,11 @@ def run_ising(L: int, T: float, n_chains: int, therm: int, meas: int, ac_len: in
     m2 = analysis.mean_and_error(st["sum_m2"] / nm / n ** 2)
     ser = b.sweep(ac_len, measure=False, series=True)[:, :, 0].double().cpu().numpy()
     a = analysis.autocorrelation(ser, min(400, ac_len // 4))
+    # %OL (20 bins on [0, 1]) of the |M| distribution k sweeps after random starts against the
+    # thermalised one
+    am_eq = np.abs(ser).ravel() / n
+    ol = {str(k): analysis.percent_overlap(am[:, k - 1], am_eq, 20, (0.0, 1.0))
+          for k in (10, 30, 100, 300) if k <= conv_len}
     a_abs = analysis.autocorrelation(np.abs(ser), min(400, ac_len // 4))
     ups = n_chains * meas * n / sec
     out = {"workload": f"ising{L}x{L}_T{T:g}", "L": L, "T": T, "J": 1.0, "chains": n_chains,
@@ -313,6 +334,7 @@ def run_ising(L: int, T: float, n_chains: int, therm: int, meas: int, ac_len: in
            "convergence_abs_M_se": {str(k): float(curve_se[k - 1]) for k in (1, 30, 100, 300) if k <= conv_len},
            "autocorr_M": {str(t): float(a[t]) for t in (1, 10, 50, 100, 200, 400) if t < len(a)},
            "tau_int_M": analysis.integrated_time(a), "tau_int_abs_M": analysis.integrated_time(a_abs),
+           "percent_overlap_abs_M_vs_thermalised": ol,
            "ms_per_sweep": sec * 1e3 / meas, "updates_per_s": ups,
            "roofline": {"bound": "alu", "achieved": ups * ISING_OPS_PER_UPDATE / 1e12,
                         "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-op/s",
