@@ -169,6 +169,7 @@ class Model:
     stab_every: int
     mu: float = 0.0
     exact_pivot: bool = False   # UDT by udt_exact_pivot instead of LAPACK's pivoted QR
+    sweep_mode: int = 0         # bit 0: alternate up and down sweeps; bit 1: per-slice measurements
 
     def __post_init__(self):
         self.T = np.asarray(self.T, dtype=np.float64)
@@ -199,6 +200,10 @@ class Model:
     def wrap(self, G, s_l, sigma):
         """G(l) = B_l G(l-1) B_l^{-1}: [I + B(l,0)B(L,l)]^{-1} conjugated by B_l."""
         return self.B(s_l, sigma) @ G @ self.Binv(s_l, sigma)
+
+    def unwrap(self, G, s_l, sigma):
+        """G(l-1) = B_l^{-1} G(l) B_l, the wrap run backwards (down sweeps)."""
+        return self.Binv(s_l, sigma) @ G @ self.B(s_l, sigma)
 
     def ratios(self, G_up, G_dn, s_l):
         """Per-site ratios for flipping s_{i,l} alone, given G(l) of both spins.
@@ -266,6 +271,9 @@ class ChainState:
     max_drift: float = 0.0
     max_logdet_err: float = 0.0
     flags: int = 0
+    slice_docc: float = 0.0            # sums of the per-slice equal-time estimators
+    slice_kin: float = 0.0
+    slice_meas: int = 0
 
 
 class OracleChains:
@@ -290,62 +298,86 @@ class OracleChains:
             self.chains.append(st)
 
     # -- one sweep of one chain ---------------------------------------------------------
-    def _sweep_chain(self, st: ChainState):
+    def _metropolis_slice(self, st: ChainState, G_up, G_dn, l: int, logdet_run):
+        """Attempt every site of slice l (sites ascending) with G = G(l) of both spins."""
         m = self.m
-        Lt, N = m.n_slices, m.N
-        G_up, G_dn = st.G
+        s_l = st.fields[l - 1]
+        for i in range(m.N):
+            s = float(s_l[i])
+            d_up = math.exp(-2.0 * m.nu * s) - 1.0
+            d_dn = math.exp(+2.0 * m.nu * s) - 1.0
+            r_up = 1.0 + d_up * (1.0 - G_up[i, i])
+            r_dn = 1.0 + d_dn * (1.0 - G_dn[i, i])
+            R = r_up * r_dn
+            u = accept_uniform(st.seed, st.sweeps_done, l - 1, i)
+            st.attempted += 1
+            if not math.isfinite(R):
+                st.flags |= FLAG_NONFINITE
+                continue
+            if R < 0.0:
+                st.flags |= FLAG_NEGATIVE_RATIO
+                continue
+            if abs(u - R) < NEAR_TIE:
+                st.near_ties += 1
+            if u < R:
+                # Sherman-Morrison: G' = G (I + Delta (I - G))^{-1}
+                #                      = G - (Delta / R_sigma) G[:, i] (e_i - G[i, :])
+                for k, (d, r) in enumerate(((d_up, r_up), (d_dn, r_dn))):
+                    G = G_up if k == 0 else G_dn
+                    col = G[:, i].copy()
+                    row = -G[i, :].copy()
+                    row[i] += 1.0
+                    G -= (d / r) * np.outer(col, row)
+                logdet_run[0] += math.log(abs(r_up))
+                logdet_run[1] += math.log(abs(r_dn))
+                s_l[i] = -s_l[i]
+                st.accepted += 1
+        if m.sweep_mode & 2:
+            docc, _, kin = measure_from_green(m.T, G_up, G_dn)
+            st.slice_docc += docc
+            st.slice_kin += kin
+            st.slice_meas += 1
+
+    def _stabilise(self, st: ChainState, Gs, l: int, logdet_run):
+        """Replace the running G(l) of both spins by the fresh one; record drift and log-det error."""
+        m = self.m
+        for k, sigma in enumerate((+1, -1)):
+            G_new, ld = m.green(st.fields, l, sigma)
+            drift = float(np.max(np.abs(Gs[k] - G_new)))
+            if not math.isfinite(drift):
+                st.flags |= FLAG_NONFINITE
+            st.max_drift = max(st.max_drift, drift)
+            st.max_logdet_err = max(st.max_logdet_err, abs(ld - logdet_run[k]))
+            logdet_run[k] = ld
+            Gs[k] = G_new
+        if st.max_drift > DRIFT_LIMIT:
+            st.flags |= FLAG_DRIFT
+
+    def _sweep_chain(self, st: ChainState):
+        """Up sweep: for l = 1 .. L_tau wrap to G(l), attempt slice l, stabilise at l = k n_s and
+        l = L_tau.  Down sweep (odd global sweeps when sweep_mode bit 0 is set): for l = L_tau ..
+        1 attempt slice l with G(l), unwrap to G(l-1), stabilise at l - 1 = k n_s (including 0).
+        Either way the chain ends at G(0) = G(L_tau)."""
+        m = self.m
+        Lt = m.n_slices
+        Gs = [st.G[0], st.G[1]]
         logdet_run = list(st.logdet)
-        for l in range(1, Lt + 1):
-            s_l = st.fields[l - 1]
-            G_up = m.wrap(G_up, s_l, +1)
-            G_dn = m.wrap(G_dn, s_l, -1)
-            for i in range(N):
-                s = float(s_l[i])
-                d_up = math.exp(-2.0 * m.nu * s) - 1.0
-                d_dn = math.exp(+2.0 * m.nu * s) - 1.0
-                r_up = 1.0 + d_up * (1.0 - G_up[i, i])
-                r_dn = 1.0 + d_dn * (1.0 - G_dn[i, i])
-                R = r_up * r_dn
-                u = accept_uniform(st.seed, st.sweeps_done, l - 1, i)
-                st.attempted += 1
-                if not math.isfinite(R):
-                    st.flags |= FLAG_NONFINITE
-                    continue
-                if R < 0.0:
-                    st.flags |= FLAG_NEGATIVE_RATIO
-                    continue
-                if abs(u - R) < NEAR_TIE:
-                    st.near_ties += 1
-                if u < R:
-                    # Sherman-Morrison: G' = G (I + Delta (I - G))^{-1}
-                    #                      = G - (Delta / R_sigma) G[:, i] (e_i - G[i, :])
-                    for k, (d, r) in enumerate(((d_up, r_up), (d_dn, r_dn))):
-                        G = G_up if k == 0 else G_dn
-                        col = G[:, i].copy()
-                        row = -G[i, :].copy()
-                        row[i] += 1.0
-                        G -= (d / r) * np.outer(col, row)
-                    logdet_run[0] += math.log(abs(r_up))
-                    logdet_run[1] += math.log(abs(r_dn))
-                    s_l[i] = -s_l[i]
-                    st.accepted += 1
-            if l % m.stab_every == 0 or l == Lt:
-                for k, sigma in enumerate((+1, -1)):
-                    G_old = G_up if k == 0 else G_dn
-                    G_new, ld = m.green(st.fields, l, sigma)
-                    drift = float(np.max(np.abs(G_old - G_new)))
-                    if not math.isfinite(drift):
-                        st.flags |= FLAG_NONFINITE
-                    st.max_drift = max(st.max_drift, drift)
-                    st.max_logdet_err = max(st.max_logdet_err, abs(ld - logdet_run[k]))
-                    logdet_run[k] = ld
-                    if k == 0:
-                        G_up = G_new
-                    else:
-                        G_dn = G_new
-                if st.max_drift > DRIFT_LIMIT:
-                    st.flags |= FLAG_DRIFT
-        st.G = [G_up, G_dn]
+        down = bool(m.sweep_mode & 1) and (st.sweeps_done % 2 == 1)
+        if not down:
+            for l in range(1, Lt + 1):
+                s_l = st.fields[l - 1]
+                Gs = [m.wrap(Gs[0], s_l, +1), m.wrap(Gs[1], s_l, -1)]
+                self._metropolis_slice(st, Gs[0], Gs[1], l, logdet_run)
+                if l % m.stab_every == 0 or l == Lt:
+                    self._stabilise(st, Gs, l, logdet_run)
+        else:
+            for l in range(Lt, 0, -1):
+                self._metropolis_slice(st, Gs[0], Gs[1], l, logdet_run)
+                s_l = st.fields[l - 1]
+                Gs = [m.unwrap(Gs[0], s_l, +1), m.unwrap(Gs[1], s_l, -1)]
+                if (l - 1) % m.stab_every == 0:
+                    self._stabilise(st, Gs, l - 1, logdet_run)
+        st.G = Gs
         st.logdet = logdet_run
         st.sweeps_done += 1
 
@@ -365,7 +397,10 @@ class OracleChains:
                             logdet_up=st.logdet[0], logdet_dn=st.logdet[1],
                             max_drift=st.max_drift, max_logdet_err=st.max_logdet_err,
                             attempted=st.attempted, accepted=st.accepted,
-                            near_ties=st.near_ties, flags=st.flags))
+                            near_ties=st.near_ties, flags=st.flags,
+                            slice_double_occ=st.slice_docc / st.slice_meas if st.slice_meas else 0.0,
+                            slice_kinetic=st.slice_kin / st.slice_meas if st.slice_meas else 0.0,
+                            slice_meas=st.slice_meas))
         return out
 
     def fields(self) -> np.ndarray:

@@ -305,25 +305,75 @@ def test_logdet_bookkeeping_and_drift():
 
 
 @pytest.mark.slow
-def test_chain_statistics_match_enumeration():
-    """2x2, U=4, L_tau=4: oracle chains sample W(s); <D> and <E_k> within 4 sigma of exact."""
+@pytest.mark.parametrize("sweep_mode", [0, 3])
+def test_chain_statistics_match_enumeration(sweep_mode):
+    """2x2, U=4, L_tau=4: oracle chains sample W(s); <D> and <E_k> within 4 sigma of exact, with
+    up sweeps only and with alternating up/down sweeps (then also the per-slice estimators)."""
     T = di.square_hopping(2)
     Lt = 4
     _, Dx, Ex = ex.enumerate_observables(T, 4.0, 0.1, Lt)
-    m = Model(T, 4.0, 0.1, Lt, 2)
+    m = Model(T, 4.0, 0.1, Lt, 2, sweep_mode=sweep_mode)
     n_chains, burn, n_meas = 24, 20, 150
     seeds = list(range(100, 100 + n_chains))
     oc = OracleChains(m, di.seeded_fields(seeds, Lt, 4), seeds)
     oc.sweep(burn)
+    start = [(o["slice_double_occ"] * o["slice_meas"], o["slice_kinetic"] * o["slice_meas"],
+              o["slice_meas"]) for o in oc.measure()]
     sums = np.zeros((n_chains, 2))
     for _ in range(n_meas):
         oc.sweep(1)
         for c, o in enumerate(oc.measure()):
             sums[c] += (o["double_occ"], o["kinetic"])
     means = sums / n_meas
-    for k, exact in enumerate((Dx, Ex)):
-        mu, se = means[:, k].mean(), means[:, k].std(ddof=1) / math.sqrt(n_chains)
-        assert abs(mu - exact) < 4 * se + 1e-12, (k, mu, se, exact)
+    checks = [(means[:, 0], Dx), (means[:, 1], Ex)]
+    if sweep_mode & 2:
+        end = oc.measure()
+        per_slice = np.array([[(o["slice_double_occ"] * o["slice_meas"] - a) / (o["slice_meas"] - n),
+                               (o["slice_kinetic"] * o["slice_meas"] - b) / (o["slice_meas"] - n)]
+                              for o, (a, b, n) in zip(end, start)])
+        assert all(o["slice_meas"] == (burn + n_meas) * Lt for o in end)
+        checks += [(per_slice[:, 0], Dx), (per_slice[:, 1], Ex)]
+    for v, exact in checks:
+        mu, se = v.mean(), v.std(ddof=1) / math.sqrt(n_chains)
+        assert abs(mu - exact) < 4 * se + 1e-12, (mu, se, exact)
+
+
+def test_unwrap_equals_fresh_green():
+    """Down sweeps move G(l) to G(l-1) = B_l^{-1} G(l) B_l: equal to the fresh G(l-1)."""
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    m = Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    f = w.fields(1)[0]
+    for l in (1, 7, 20):
+        for sigma in (+1, -1):
+            G, _ = m.green(f, l, sigma)
+            ref, _ = m.green(f, l - 1, sigma)
+            assert np.max(np.abs(m.unwrap(G, f[l - 1], sigma) - ref)) < 1e-11
+
+
+def test_alternating_sweeps_stay_on_the_fresh_green():
+    """Up then down sweeps on 4x4: every stabilisation replaces a running G within 1e-9 of the
+    fresh one (a wrong unwrap or slice order would drift at once), the chain ends at G(0)."""
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    m = Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, sweep_mode=3)
+    oc = OracleChains(m, w.fields(2), w.seeds(2))
+    oc.sweep(4)
+    for c, o in enumerate(oc.measure()):
+        assert o["max_drift"] < 1e-9 and o["flags"] == 0
+        assert o["slice_meas"] == 4 * w.n_slices
+        f = oc.fields()[c]
+        assert np.max(np.abs(oc.green()[c, 0] - m.green(f, 0, +1)[0])) < 1e-12
+
+
+def test_per_slice_estimators_free_fermions():
+    """U = 0: every field gives the free G at every slice, so the per-slice averages equal the
+    closed forms D = 1/4 and the free kinetic energy."""
+    T = di.square_hopping(4)
+    m = Model(T, 0.0, 0.1, 20, 10, sweep_mode=3)
+    oc = OracleChains(m, di.seeded_fields([3], 20, 16), [3])
+    oc.sweep(2)
+    o = oc.measure()[0]
+    assert abs(o["slice_double_occ"] - 0.25) < 1e-12
+    assert abs(o["slice_kinetic"] - ex.free_kinetic(T, 2.0)) < 1e-12
 
 
 # ------------------------------------------------------------------ spin structure factor
