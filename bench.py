@@ -105,12 +105,13 @@ def choose_qr(w, mode: str) -> bool:
 
 
 def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh: int,
-            qr_blocked: bool = False):
+            qr_blocked: bool = False, sweep_mode: int = 0):
     import torch
     from paper_2106_00712_amd import dqmc
 
     m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank,
-                        precision=precision, refresh_every=refresh, qr_blocked=qr_blocked)
+                        precision=precision, refresh_every=refresh, qr_blocked=qr_blocked,
+                        sweep_mode=sweep_mode)
     fields = torch.as_tensor(w.fields()).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -401,6 +402,8 @@ def main():
     ap.add_argument("--meas", type=int, default=400, help="with --physics: measurement sweeps")
     ap.add_argument("--qr", default="auto", choices=("auto", "pivoted", "blocked"),
                     help="with --workload / --mixed: stabilisation QR of the N > 64 kernels")
+    ap.add_argument("--sweep-mode", type=int, default=0,
+                    help="with --workload: 1 alternating up/down sweeps, 2 per-slice measurements, 3 both")
     ap.add_argument("--ising", action="store_true",
                     help="only the Ising workload: Table 1 at L=16, T=2.269, plus L=32 dynamics")
     ap.add_argument("--ising-meas", type=int, default=20000, help="with --ising: measured sweeps at L=16")
@@ -419,7 +422,8 @@ def main():
                              args.chains, wl.n_sweeps, wl.stab_every)
         qb = choose_qr(wl, args.qr)
         r = run_gpu(wl, args.precision, args.steps, args.warmup, args.delay_rank,
-                    (args.refresh or 10) if args.precision == "fp32_wrap" else 0, qr_blocked=qb)
+                    (args.refresh or 10) if args.precision == "fp32_wrap" else 0, qr_blocked=qb,
+                    sweep_mode=args.sweep_mode)
         o = r["obs"]
         ups = wl.n_chains * wl.n_slices * wl.n_sites
         acc = float(o["accepted"].sum() / max(1, o["attempted"].sum()))
@@ -431,7 +435,8 @@ def main():
                           "tflops": flw["total"] * wl.n_chains / tl / 1e12,
                           "frac_fp64_peak": flw["total"] * wl.n_chains / tl / PEAK_FP64_MFMA,
                           "kernel_variant": r["batch"].variant, "delay_rank": r["batch"].delay_rank,
-                          "stab": r["batch"].stab, "qr_blocked": qb, "init_ms": r["init_ms"],
+                          "stab": r["batch"].stab, "qr_blocked": qb, "sweep_mode": args.sweep_mode,
+                          "init_ms": r["init_ms"],
                           "max_drift": float(o["max_drift"].max()),
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),

@@ -73,6 +73,12 @@ typedef struct {
                                large N).  It reproduces the pivoted G only while the products are
                                mildly graded; enable it for a model only after checking that on
                                fixed fields (the autotuner does).  Ignored elsewhere. */
+  int32_t sweep_mode;       /* 0: every sweep an up sweep (slices 1 .. L_tau), right UDT stack
+                               rebuilt per sweep.  Bit 0: odd global sweeps run down (attempt
+                               slice l at G(l), then G(l-1) = B_l^{-1} G(l) B_l), each direction
+                               reusing the UDT stack the other one left.  Bit 1: the equal-time
+                               estimators are also taken after every slice (dqmc_obs.slice_*).
+                               Nonzero modes run in the workspace kernels at any N. */
 } dqmc_model;
 
 /* Observables of one chain, written by dqmc_measure (device memory, one per chain).  The
@@ -92,6 +98,9 @@ typedef struct {
   int64_t sweeps_done;    /* global sweep counter of the chain (RNG counter, resume point) */
   int32_t flags;          /* DQMC_FLAG_* */
   int32_t reserved;
+  double slice_double_occ; /* per-slice estimators (sweep_mode bit 1), averaged over every slice */
+  double slice_kinetic;    /*   of every sweep since init; 0 without measurements */
+  int64_t slice_meas;      /* number of slices measured */
 } dqmc_obs;
 
 typedef struct dqmc_batch dqmc_batch;   /* opaque host handle */
@@ -181,7 +190,9 @@ dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int3
 
 /* Fresh G^sigma(slice) = [I + B(slice,0) B(L_tau,slice)]^{-1} of every chain's current field,
  * then n_wraps wraps G <- B_l G B_l^{-1} (l = slice+1 .. slice+n_wraps) in the batch's wrap
- * precision.  out: DEVICE double [n_chains][2][N][N].  0 <= slice, slice + n_wraps <= L_tau. */
+ * precision, or for n_wraps < 0 the down sweeps' unwraps G <- B_l^{-1} G B_l (l = slice,
+ * slice-1, .., slice+n_wraps+1).  out: DEVICE double [n_chains][2][N][N].
+ * 0 <= slice <= L_tau, 0 <= slice + n_wraps <= L_tau. */
 dqmc_status dqmc_debug_green(dqmc_batch* b, int32_t slice, int32_t n_wraps, double* out,
                              void* stream);
 

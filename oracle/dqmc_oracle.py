@@ -412,7 +412,8 @@ class OracleChains:
 
     # -- fixed-field probes (no acceptance, no state change) -----------------------------
     def debug_green(self, l: int, n_wraps: int) -> np.ndarray:
-        """Fresh G(l) of the current fields, then wrapped through slices l+1 .. l+n_wraps."""
+        """Fresh G(l) of the current fields, then wrapped through slices l+1 .. l+n_wraps, or
+        for n_wraps < 0 unwrapped through slices l, l-1, .. l+n_wraps+1 (G(l-1) = B_l^-1 G B_l)."""
         out = []
         for st in self.chains:
             per = []
@@ -420,6 +421,8 @@ class OracleChains:
                 G, _ = self.m.green(st.fields, l, sigma)
                 for w in range(1, n_wraps + 1):
                     G = self.m.wrap(G, st.fields[l + w - 1], sigma)
+                for w in range(0, -n_wraps):
+                    G = self.m.unwrap(G, st.fields[l - w - 1], sigma)
                 per.append(G)
             out.append(np.stack(per))
         return np.stack(out)

@@ -111,6 +111,10 @@ __global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
       st->flags = 0;
       st->pad = 0;
       for (int k = 0; k < 16; ++k) st->ticks[k] = 0;
+      st->slice_docc = st->slice_kin = 0.0;
+      st->slice_meas = 0;
+      st->stack_ok = 0;
+      st->pad2 = 0;
     }
     __syncthreads();
     op_init(c, idx);
@@ -183,6 +187,9 @@ __global__ __launch_bounds__(NT) void measure_kernel(KArgs a, dqmc_obs* obs, dou
     o.sweeps_done = st->sweeps_done;
     o.flags = st->flags;
     o.reserved = 0;
+    o.slice_double_occ = st->slice_meas ? st->slice_docc / st->slice_meas : 0.0;
+    o.slice_kinetic = st->slice_meas ? st->slice_kin / st->slice_meas : 0.0;
+    o.slice_meas = st->slice_meas;
     obs[chain] = o;
   }
   if (green) {
@@ -313,7 +320,7 @@ struct Layout {
   size_t c_expK, c_expKinv, c_expK32, c_expKinv32, c_T, c_eye, c_ones, c_A, c_E0, c_E1, c_seeds,
       c_slots, c_err, c_end;
   // per chain
-  size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, o_qrv, stride;
+  size_t o_stats, o_fields, o_G64, o_stack, o_left, o_Gw, o_work, o_xy, o_qrv, o_lstack, stride;
   int KT;   // accumulated delayed-update rank (workspace variant), 0 otherwise
 };
 
@@ -341,6 +348,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
     return fail(DQMC_EINVAL, "unknown precision");
   if (m->refresh_every < 0 || m->delay_rank < 0) return fail(DQMC_EINVAL, "negative refresh/delay");
   if (m->qr_blocked != 0 && m->qr_blocked != 1) return fail(DQMC_EINVAL, "qr_blocked must be 0 or 1");
+  if (m->sweep_mode < 0 || m->sweep_mode > 3) return fail(DQMC_EINVAL, "sweep_mode must be in [0, 3]");
   if (n_chains < 0) return fail(DQMC_EINVAL, "n_chains must be >= 0");
   Layout L{};
   L.n = m->n_sites;
@@ -367,7 +375,8 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   int k_small = std::min(kreq, 16);
   k_small = std::min(k_small, (int)(wts == 8 ? L.np / 2 : L.np));
   k_small = std::max(4, k_small & ~3);
-  L.small = small_bytes(k_small) <= (size_t)lds_limit;
+  // the sweep modes (alternating sweeps, per-slice measurements) run in the workspace kernels
+  L.small = m->sweep_mode == 0 && small_bytes(k_small) <= (size_t)lds_limit;
   if (L.small) {
     L.K = k_small;
     L.lds_bytes = small_bytes(L.K);
@@ -379,7 +388,7 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   // fast sweep path: padded size 16, 32 or 64, block size 8 or 16 sites
   L.fast = false;
   L.fast_lds_bytes = 0;
-  if (L.np == 16 || L.np == 32 || L.np == 64) {
+  if (m->sweep_mode == 0 && (L.np == 16 || L.np == 32 || L.np == 64)) {
     const int kb = (kreq <= 8 || L.np == 16) ? 8 : 16;
     size_t fb = 0;
     const bool f32 = wts == 4;
@@ -434,8 +443,10 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
     // blocked factorisations (np <= QR_BLOCK_MAX_NP): QR reflectors (np x np) and one QB x QB
     // T per panel; the Gauss-Jordan solve reuses the first 3 QB np doubles
     L.o_qrv = (L.np <= QR_BLOCK_MAX_NP) ? ctake((nn + (size_t)QB * L.np) * 8) : 0;
+    // left UDT stack of the alternating sweeps, laid out like the right stack
+    L.o_lstack = (m->sweep_mode & 1) ? ctake(2 * (size_t)L.J * (2 * nn + L.np) * 8) : 0;
   } else {
-    L.o_work = L.o_xy = L.o_qrv = 0;
+    L.o_work = L.o_xy = L.o_qrv = L.o_lstack = 0;
     L.KT = 0;
   }
   L.stride = align256(co);
@@ -470,6 +481,8 @@ void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KAr
   a->o_fields = L.o_fields; a->o_G64 = L.o_G64; a->o_Gw = L.o_Gw; a->o_stack = L.o_stack;
   a->o_left = L.o_left; a->o_work = L.o_work; a->o_xy = L.o_xy; a->o_stats = L.o_stats;
   a->o_qrv = L.o_qrv;
+  a->o_lstack = L.o_lstack;
+  a->sweep_mode = m->sweep_mode;
   a->qr_blocked = m->qr_blocked;
 }
 
@@ -763,7 +776,8 @@ dqmc_status dqmc_batch_info(const dqmc_batch* b, int32_t* k, int32_t* stab, int3
 
 dqmc_status dqmc_debug_green(dqmc_batch* b, int32_t slice, int32_t n_wraps, double* out, void* stream) {
   if (!b || !out) return fail(DQMC_EINVAL, "batch/out is NULL");
-  if (slice < 0 || n_wraps < 0 || slice + n_wraps > b->L) return fail(DQMC_EINVAL, "slice range");
+  if (slice < 0 || slice > b->L || slice + n_wraps < 0 || slice + n_wraps > b->L)
+    return fail(DQMC_EINVAL, "slice range");
   KArgs a = b->args;
   a.op = OP_DEBUG_GREEN;
   a.slice = slice;

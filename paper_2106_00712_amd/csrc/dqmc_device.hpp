@@ -39,6 +39,10 @@ struct ChainStats {
   double logdet[2];
   int32_t flags, pad;
   int64_t ticks[16];  // wall-clock ticks (100 MHz) spent per phase, see enum Phase
+  double slice_docc, slice_kin;   // sums of the per-slice equal-time estimators
+  int64_t slice_meas;
+  int32_t stack_ok;   // the right UDT stack describes the current fields (alternating sweeps)
+  int32_t pad2;
 };
 
 // Phases of a sweep timed by thread 0 between workgroup barriers.
@@ -59,6 +63,7 @@ struct PhaseClock {
 struct KArgs {
   int n, np, L, stab, J, K, n_chains, op, slice, n_wraps, n_sweeps, gen_fields;
   int KT;               // accumulated delayed-update rank of the N > 64 workspace kernels (0: none)
+  int sweep_mode;       // bit 0: alternating up/down sweeps, bit 1: per-slice measurements
   double nu, drift_limit;
   double ev[2];     // e^{+nu}, e^{-nu}
   double dup[2];    // Delta^up(s)   = e^{-2 nu s} - 1 for s = -1 (index 0), s = +1 (index 1)
@@ -79,6 +84,7 @@ struct KArgs {
   size_t stride;        // bytes per chain
   size_t o_fields, o_G64, o_Gw, o_stack, o_left, o_work, o_xy, o_stats;
   size_t o_qrv;         // scratch of the blocked factorisations (0: unblocked only)
+  size_t o_lstack;      // left UDT stack of the alternating sweeps (0: none)
   int qr_blocked;       // stabilisation QR: 1 blocked with pre-sorted columns, 0 column-pivoted
   double* out;
 };
@@ -315,6 +321,7 @@ struct Ctx {
   double* stack;      // right UDT stack [2][J][U, T, d]
   double* left;       // left UDT [2][U, T0, T1, d]
   double* qrv;        // blocked QR: reflectors V (np x np, column-major) then T factors, or NULL
+  double* lstack;     // left UDT stack [2][J][U, T, d] of the alternating sweeps, or NULL
   // LDS vectors
   double *vd, *bt, *nrm, *dtmp, *sr, *sc;   // sr/sc: [2][np] row/column scale factors
   int* ordv;          // [np] pivot order / used marks
@@ -360,6 +367,7 @@ __device__ inline Ctx<WT> make_ctx(const KArgs& a, int chain, double* lds) {
   c.stack = (double*)(cb + a.o_stack);
   c.left = (double*)(cb + a.o_left);
   c.qrv = a.o_qrv ? (double*)(cb + a.o_qrv) : nullptr;
+  c.lstack = a.o_lstack ? (double*)(cb + a.o_lstack) : nullptr;
   double* p = lds;
   if (SMALL) {
     WT* g = (WT*)p;
@@ -1519,6 +1527,31 @@ __device__ __forceinline__ void wrap_both(Ctx<WT>& c, int l) {
   __syncthreads();
 }
 
+// G(l-1) = B_l^{-1} G(l) B_l = e^{+dtau T} V_l^{-1} G(l) V_l e^{-dtau T} for both spins (down
+// sweeps): the diagonal factors in place, then two MFMA products.
+template <typename WT>
+__device__ __forceinline__ void unwrap_both(Ctx<WT>& c, int l) {
+  const KArgs& a = *c.a;
+  const int np = c.np;
+  slice_scales(c, l - 1);
+  __syncthreads();   // the scales are read by every thread below
+  for (int e = threadIdx.x; e < 2 * np * np; e += NT) {
+    const int b = e / (np * np), r = e - b * (np * np), i = r / np, j = r - i * np;
+    c.G[b][r] = (WT)(c.sc[b * np + i] * (double)c.G[b][r] * c.sr[b * np + j]);
+  }
+  __syncthreads();
+  WT* t0 = (WT*)c.w1;
+  WT* t1 = (WT*)c.w2;
+  const WT* K1 = kexp<WT>(a);
+  const WT* K2 = kexpinv<WT>(a);
+  ctx_gemm<WT>(c, 2, np, np, np, K2, K2, np, 1, c.G[0], c.G[1], np, 1,
+               [&](int b, int i, int j, WT v) { (b ? t1 : t0)[i * np + j] = v; });
+  __syncthreads();
+  ctx_gemm<WT>(c, 2, np, np, np, t0, t1, np, 1, K1, K1, np, 1,
+               [&](int b, int i, int j, WT v) { c.G[b][i * np + j] = v; });
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------------------ Metropolis
 // Single-flip Metropolis over the sites of slice l with submatrix (delayed) updates.
 //
@@ -1885,6 +1918,52 @@ __device__ __forceinline__ double* lftT(Ctx<WT>& c, int sp, int k) { return lftU
 template <typename WT>
 __device__ __forceinline__ double* lftD(Ctx<WT>& c, int sp) { return lftU(c, sp) + 3 * (size_t)c.np * c.np; }
 
+// Left stack of the alternating sweeps: entry j = UDT of B(j*stab, 0), written by up sweeps.
+template <typename WT>
+__device__ __forceinline__ double* lstkU(Ctx<WT>& c, int sp, int j) {
+  const size_t nn = (size_t)c.np * c.np;
+  return c.lstack + ((size_t)sp * c.J + j) * (2 * nn + c.np);
+}
+template <typename WT>
+__device__ __forceinline__ double* lstkT(Ctx<WT>& c, int sp, int j) { return lstkU(c, sp, j) + (size_t)c.np * c.np; }
+template <typename WT>
+__device__ __forceinline__ double* lstkD(Ctx<WT>& c, int sp, int j) { return lstkU(c, sp, j) + 2 * (size_t)c.np * c.np; }
+
+// Equal-time estimators of the current G(l) (after every attempt of slice l, both directions),
+// added to the chain's per-slice sums: double occupancy and kinetic energy per site as in
+// measure_kernel.
+template <typename WT>
+__device__ __forceinline__ void slice_measure(Ctx<WT>& c) {
+  const KArgs& a = *c.a;
+  const int n = c.n, np = c.np, tid = threadIdx.x;
+  double docc = 0.0, kin = 0.0;
+  for (int i = tid; i < n; i += NT) {
+    const double gu = (double)c.G[0][i * np + i], gd = (double)c.G[1][i * np + i];
+    docc += (1.0 - gu) * (1.0 - gd);
+  }
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, j = e - i * n;
+    const double t = a.Tm[i * np + j];
+    if (t != 0.0)
+      kin += t * (2.0 * (i == j ? 1.0 : 0.0) - (double)c.G[0][j * np + i] - (double)c.G[1][j * np + i]);
+  }
+  docc = wave_sum(docc);
+  kin = wave_sum(kin);
+  if ((tid & 63) == 0) {
+    c.red.v[tid >> 6] = docc;
+    c.red.v[NW + (tid >> 6)] = kin;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < NW; ++w) { s0 += c.red.v[w]; s1 += c.red.v[NW + w]; }
+    c.st->slice_docc += s0 / n;
+    c.st->slice_kin += s1 / n;
+    c.st->slice_meas += 1;
+  }
+  __syncthreads();
+}
+
 // Build stack entries j = J-1 down to j_lo: entry j = UDT of B(L, j*stab)^T.
 template <typename WT>
 __device__ __forceinline__ void build_right(Ctx<WT>& c, int j_lo) {
@@ -1941,60 +2020,126 @@ __device__ __forceinline__ void op_init(Ctx<WT>& c, int idx) {
                 c.G64 + (size_t)sp * np * np, &ld, false);
     if (tid == 0) c.st->logdet[sp] = ld;
   }
+  if (tid == 0) c.st->stack_ok = 1;
   __syncthreads();
 }
 
+// Fresh-G bookkeeping of one spin at a stabilisation point: drift, log-det error, flags.
+template <typename WT>
+__device__ __forceinline__ void stab_record(Ctx<WT>& c, int sp, double dr, double ld, double* ldrun) {
+  const KArgs& a = *c.a;
+  if (threadIdx.x == 0) {
+    ChainStats* st = c.st;
+    if (dr > st->max_drift || dr != dr) st->max_drift = dr;
+    if (!(dr <= a.drift_limit)) st->flags |= FLAG_DRIFT;
+    double e = fabs(ld - ldrun[sp]);
+    if (e > st->max_logdet_err) st->max_logdet_err = e;
+    ldrun[sp] = ld;
+  }
+  __syncthreads();
+}
+
+// n_sweeps sweeps.  Up sweep: wrap to G(l), attempt slice l, and at l = k stab and l = L push
+// the chunk onto the left UDT and take the fresh G(l) from it and the right stack entry (built
+// afresh at the start of the sweep, or left by the previous down sweep).  Down sweep (odd global
+// sweeps of the alternating mode): attempt slice l at G(l), unwrap to G(l-1), and at
+// l - 1 = k stab push the chunk onto the right UDT (into stack entry k) and take the fresh G from
+// it and the left stack entry k written by the previous up sweep.
 template <typename WT>
 __device__ __forceinline__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
   const KArgs& a = *c.a;
   const int np = c.np, L = c.L, tid = threadIdx.x;
+  const bool alt = (a.sweep_mode & 1) && c.lstack;
+  const bool per_slice = (a.sweep_mode & 2) != 0;
   load_green(c);
   PhaseClock clk, total;
   for (int s = 0; s < n_sweeps; ++s) {
     total.start();
-    clk.start();
-    build_right(c, 1);
-    clk.stop(c.st, PH_RIGHT);
     double* ldrun = c.misc;   // running log|det| per spin from accepted ratios
+    const bool down = alt && (c.st->sweeps_done & 1);
+    const bool stack_ok = c.st->stack_ok != 0;
+    __syncthreads();
     if (tid == 0) { ldrun[0] = c.st->logdet[0]; ldrun[1] = c.st->logdet[1]; }
     __syncthreads();
-    int cur = 0;     // which left T buffer is current
-    int l_prev = 0;  // last stabilisation slice
-    for (int l = 1; l <= L; ++l) {
+    if (!down) {
       clk.start();
-      wrap_both(c, l);
-      clk.stop(c.st, PH_WRAP);
-      if (c.stage && a.KT > 0) metropolis_slice2(c, l, ldrun);
-      else metropolis_slice(c, l, ldrun);
-      __syncthreads();
-      clk.start();
-      if (l % c.stab == 0 || l == L) {
-        const int jr = l / c.stab;   // stack entry at l (unused when l == L)
-        for (int sp = 0; sp < 2; ++sp) {
-          const bool first = (l_prev == 0);
-          udt_push(c, sp, false, l_prev, l, first ? a.eye : lftU(c, sp), first ? a.ones : lftD(c, sp),
-                   first ? a.eye : lftT(c, sp, cur), lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1));
-          clk.stop(c.st, PH_LEFT);
-          double ld;
+      if (!alt || !stack_ok) build_right(c, 1);
+      clk.stop(c.st, PH_RIGHT);
+      int cur = 0;     // which left T buffer is current
+      int l_prev = 0;  // last stabilisation slice
+      for (int l = 1; l <= L; ++l) {
+        clk.start();
+        wrap_both(c, l);
+        clk.stop(c.st, PH_WRAP);
+        if (c.stage && a.KT > 0) metropolis_slice2(c, l, ldrun);
+        else metropolis_slice(c, l, ldrun);
+        __syncthreads();
+        if (per_slice) slice_measure(c);
+        clk.start();
+        if (l % c.stab == 0 || l == L) {
+          const int jr = l / c.stab;   // stack entry at l (unused when l == L)
           const bool last = (l == L);
-          double dr = fresh_green(c, sp, lftU(c, sp), lftD(c, sp), lftT(c, sp, cur ^ 1),
-                                  last ? a.eye : stkU(c, sp, jr), last ? a.ones : stkD(c, sp, jr),
-                                  last ? a.eye : stkT(c, sp, jr),
-                                  last ? c.G64 + (size_t)sp * np * np : nullptr, &ld, true);
-          if (tid == 0) {
-            ChainStats* st = c.st;
-            if (dr > st->max_drift || dr != dr) st->max_drift = dr;
-            if (!(dr <= a.drift_limit)) st->flags |= FLAG_DRIFT;
-            double e = fabs(ld - ldrun[sp]);
-            if (e > st->max_logdet_err) st->max_logdet_err = e;
-            ldrun[sp] = ld;
+          for (int sp = 0; sp < 2; ++sp) {
+            const bool first = (l_prev == 0);
+            double *Ud, *dd, *Td;
+            if (alt) {
+              const int jp = l_prev / c.stab;
+              Ud = last ? lftU(c, sp) : lstkU(c, sp, jr);
+              dd = last ? lftD(c, sp) : lstkD(c, sp, jr);
+              Td = last ? lftT(c, sp, 0) : lstkT(c, sp, jr);
+              udt_push(c, sp, false, l_prev, l, first ? a.eye : lstkU(c, sp, jp),
+                       first ? a.ones : lstkD(c, sp, jp), first ? a.eye : lstkT(c, sp, jp), Ud, dd, Td);
+            } else {
+              Ud = lftU(c, sp);
+              dd = lftD(c, sp);
+              Td = lftT(c, sp, cur ^ 1);
+              udt_push(c, sp, false, l_prev, l, first ? a.eye : lftU(c, sp), first ? a.ones : lftD(c, sp),
+                       first ? a.eye : lftT(c, sp, cur), Ud, dd, Td);
+            }
+            clk.stop(c.st, PH_LEFT);
+            double ld;
+            double dr = fresh_green(c, sp, Ud, dd, Td, last ? a.eye : stkU(c, sp, jr),
+                                    last ? a.ones : stkD(c, sp, jr), last ? a.eye : stkT(c, sp, jr),
+                                    last ? c.G64 + (size_t)sp * np * np : nullptr, &ld, true);
+            stab_record(c, sp, dr, ld, ldrun);
+            clk.stop(c.st, PH_FRESH);
           }
-          __syncthreads();
-          clk.stop(c.st, PH_FRESH);
+          cur ^= 1;
+          l_prev = l;
         }
-        cur ^= 1;
-        l_prev = l;
       }
+      if (tid == 0) c.st->stack_ok = 0;   // the fields changed under the right stack
+    } else {
+      int r_prev = L;   // the right UDT covers B(L, r_prev)
+      for (int l = L; l >= 1; --l) {
+        if (c.stage && a.KT > 0) metropolis_slice2(c, l, ldrun);
+        else metropolis_slice(c, l, ldrun);
+        __syncthreads();
+        if (per_slice) slice_measure(c);
+        clk.start();
+        unwrap_both(c, l);
+        clk.stop(c.st, PH_WRAP);
+        if ((l - 1) % c.stab == 0) {
+          const int j = (l - 1) / c.stab;
+          const bool top = (r_prev == L);
+          const int jp = r_prev / c.stab;
+          for (int sp = 0; sp < 2; ++sp) {
+            udt_push(c, sp, true, l - 1, r_prev, top ? a.eye : stkU(c, sp, jp),
+                     top ? a.ones : stkD(c, sp, jp), top ? a.eye : stkT(c, sp, jp), stkU(c, sp, j),
+                     stkD(c, sp, j), stkT(c, sp, j));
+            clk.stop(c.st, PH_RIGHT);
+            double ld;
+            const bool bottom = (j == 0);
+            double dr = fresh_green(c, sp, bottom ? a.eye : lstkU(c, sp, j), bottom ? a.ones : lstkD(c, sp, j),
+                                    bottom ? a.eye : lstkT(c, sp, j), stkU(c, sp, j), stkD(c, sp, j),
+                                    stkT(c, sp, j), bottom ? c.G64 + (size_t)sp * np * np : nullptr, &ld, true);
+            stab_record(c, sp, dr, ld, ldrun);
+            clk.stop(c.st, PH_FRESH);
+          }
+          r_prev = l - 1;
+        }
+      }
+      if (tid == 0) c.st->stack_ok = 1;   // entries 0 .. J-1 now describe the current fields
     }
     if (tid == 0) {
       c.st->logdet[0] = ldrun[0];
@@ -2010,6 +2155,7 @@ __device__ __forceinline__ void op_sweep(Ctx<WT>& c, int n_sweeps) {
 // slice L, both chunked by stab), into the working G of both spins.
 template <typename WT>
 __device__ __forceinline__ void fresh_at(Ctx<WT>& c, int slice) {
+  if (threadIdx.x == 0) c.st->stack_ok = 0;   // stack entries 0 and 1 serve as scratch below
   const KArgs& a = *c.a;
   const int L = c.L;
   for (int sp = 0; sp < 2; ++sp) {
@@ -2047,6 +2193,7 @@ __device__ __forceinline__ void op_debug_green(Ctx<WT>& c, int chain) {
   const int n = c.n, np = c.np;
   fresh_at(c, a.slice);
   for (int w = 1; w <= a.n_wraps; ++w) wrap_both(c, a.slice + w);
+  for (int w = 0; w < -a.n_wraps; ++w) unwrap_both(c, a.slice - w);
   double* out = a.out + (size_t)chain * 2 * n * n;
   for (int e = threadIdx.x; e < 2 * n * n; e += NT) {
     int sp = e / (n * n), r = (e / n) % n, col = e % n;

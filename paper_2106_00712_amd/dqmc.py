@@ -35,14 +35,16 @@ class Model(ctypes.Structure):
                 ("U", ctypes.c_double), ("mu", ctypes.c_double), ("dtau", ctypes.c_double),
                 ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("delay_rank", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("qr_blocked", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("qr_blocked", ctypes.c_int32),
+                ("sweep_mode", ctypes.c_int32)]
 
 
 OBS_DTYPE = np.dtype([("double_occ", "f8"), ("density", "f8"), ("kinetic", "f8"),
                       ("logdet_up", "f8"), ("logdet_dn", "f8"), ("max_drift", "f8"),
                       ("max_logdet_err", "f8"), ("attempted", "i8"), ("accepted", "i8"),
                       ("near_ties", "i8"), ("sweeps_done", "i8"), ("flags", "i4"),
-                      ("reserved", "i4")])
+                      ("reserved", "i4"), ("slice_double_occ", "f8"), ("slice_kinetic", "f8"),
+                      ("slice_meas", "i8")])
 
 _lib = None
 _vp, _i32, _u64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
@@ -121,7 +123,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, delay_rank=0,
-               precision="fp64", qr_blocked=False):
+               precision="fp64", qr_blocked=False, sweep_mode=0):
     """Build the C model struct; the returned object keeps the host hopping array alive."""
     T = np.ascontiguousarray(np.asarray(hopping, dtype=np.float64))
     if T.ndim != 2 or T.shape[0] != T.shape[1]:
@@ -134,6 +136,7 @@ def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, 
     m.refresh_every, m.delay_rank = int(refresh_every), int(delay_rank)
     m.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     m.qr_blocked = 1 if qr_blocked else 0
+    m.sweep_mode = int(sweep_mode)
     m._keep = T
     return m
 
