@@ -167,7 +167,7 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
             "pool_capacity": capacity, "tick_sweeps": tick}
 
 
-def run_mixed(steps: int, refresh: int, n_each: int, qr_mode: str = "auto"):
+def run_mixed(steps: int, refresh: int, n_each: int, qr_mode: str = "auto", sweep_mode: int = 0):
     """Honeycomb 6x6 (N = 72) and 12x12 (N = 288) chains side by side in one recorded graph,
     FP32 wraps with FP64 refresh every `refresh` slices, against the same batches in FP64."""
     import torch
@@ -175,12 +175,13 @@ def run_mixed(steps: int, refresh: int, n_each: int, qr_mode: str = "auto"):
     ws = [di.WORKLOADS["honeycomb6x6_U3_b6"], di.WORKLOADS["honeycomb12x12_U3_b6"]]
     qrb = [choose_qr(w, qr_mode) for w in ws]
     out = {"workload": "honeycomb 6x6 + 12x12, U=3, beta=6", "chains_each": n_each, "steps": steps,
-           "qr_blocked": qrb}
+           "qr_blocked": qrb, "sweep_mode": sweep_mode}
     for prec in ("fp64", "fp32_wrap"):
         bs = []
         for w, qb in zip(ws, qrb):
             m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, precision=prec,
-                                refresh_every=refresh if prec == "fp32_wrap" else 0, qr_blocked=qb)
+                                refresh_every=refresh if prec == "fp32_wrap" else 0, qr_blocked=qb,
+                                sweep_mode=sweep_mode)
             bs.append(dqmc.Batch(m, w.seeds(n_each), w.fields(n_each)))
         g = dqmc.Graph(bs, [1, 1])
         g.launch()
@@ -403,7 +404,8 @@ def main():
     ap.add_argument("--qr", default="auto", choices=("auto", "pivoted", "blocked"),
                     help="with --workload / --mixed: stabilisation QR of the N > 64 kernels")
     ap.add_argument("--sweep-mode", type=int, default=0,
-                    help="with --workload: 1 alternating up/down sweeps, 2 per-slice measurements, 3 both")
+                    help="with --workload / --mixed: 1 alternating up/down sweeps, 2 per-slice "
+                         "measurements, 3 both")
     ap.add_argument("--ising", action="store_true",
                     help="only the Ising workload: Table 1 at L=16, T=2.269, plus L=32 dynamics")
     ap.add_argument("--ising-meas", type=int, default=20000, help="with --ising: measured sweeps at L=16")
@@ -452,7 +454,8 @@ def main():
         print(json.dumps(run_physics(args.chains or 256, args.therm, args.meas)))
         return
     if args.mixed:
-        print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256, args.qr)))
+        print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256, args.qr,
+                                   args.sweep_mode)))
         return
     if args.serving_full:
         out = [run_serving(rate, 48, di.SERVING_L, "fp64", 16, 10, 0) for rate in (50, 2000)]

@@ -1567,6 +1567,72 @@ __device__ __forceinline__ void unwrap_both(Ctx<WT>& c, int l) {
 //     X[r,m] = -(Delta_m/R_m) (G0[r, j_m] + sum_{m'<m} X[r,m'] Y[m', j_m])
 //     Y[m,c] = delta_{c,j_m} - G0[j_m, c] - sum_{m'<m} X[j_m, m'] Y[m', c]
 // and the rank-m correction applied as one MFMA product.
+// One wavefront decides the kb sites i0 .. i0+kb-1 of slice l in order, with the block of the
+// true G of both spins in c.gb: ratio, Philox uniform, Metropolis test, and on acceptance the
+// block's own rank-1 update and the block parts of the Sherman-Morrison vectors (x_m rows in xb,
+// y_m columns in yb, both spins), the accepted site, its two coefficients and the field flip.
+// The number accepted goes to c.cnt[0]; log|R| per spin is added to ldrun.  Run by wave 0.
+template <typename WT>
+__device__ __forceinline__ void decide_block(Ctx<WT>& c, int l, int i0, int kb, uint64_t seed,
+                                             int64_t sweep, int8_t* fl, double* ldrun) {
+  const KArgs& a = *c.a;
+  const int K = c.K, K2 = K * K, lane = threadIdx.x & 63;
+  if (lane < kb) {
+    c.ublk[lane] = accept_uniform(seed, sweep, l - 1, i0 + lane);
+    c.sblk[lane] = fl[i0 + lane];
+  }
+  wave_sync();
+  int m = 0;
+  double ldu = 0.0, ldd = 0.0;
+  int flg = 0;
+  int64_t ties = 0;
+  for (int ii = 0; ii < kb; ++ii) {
+    const int s = c.sblk[ii];
+    const double u = c.ublk[ii];
+    const double gu = c.gb[ii * K + ii], gd = c.gb[K2 + ii * K + ii];
+    const double du = a.dup[s > 0], dd = a.ddn[s > 0];
+    const double ru = 1.0 + du * (1.0 - gu), rd = 1.0 + dd * (1.0 - gd);
+    const double R = ru * rd;
+    bool ok = true;
+    if (!(fabs(R) < 1e300)) { flg |= FLAG_NONFINITE; ok = false; }
+    else if (R < 0.0) { flg |= FLAG_NEGATIVE; ok = false; }
+    if (ok && fabs(u - R) < 1e-9) ++ties;
+    if (ok && u < R) {
+      const double cu = du / ru, cd = dd / rd;
+      if (lane < kb) {
+        const int r = lane;
+        c.xb[r * K + m] = -cu * c.gb[r * K + ii];
+        c.xb[K2 + r * K + m] = -cd * c.gb[K2 + r * K + ii];
+        c.yb[m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[ii * K + r];
+        c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
+      }
+      wave_sync();
+      for (int e = lane; e < kb * kb; e += 64) {
+        int r = e / kb, cc = e - r * kb;
+        c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
+        c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
+      }
+      if (lane == 0) {
+        c.site[m] = ii;
+        c.cfu[m] = cu;
+        c.cfd[m] = cd;
+        fl[i0 + ii] = (int8_t)(-s);
+      }
+      ldu += log(fabs(ru));
+      ldd += log(fabs(rd));
+      ++m;
+      wave_sync();
+    }
+  }
+  if (lane == 0) {
+    c.cnt[0] = m;
+    ldrun[0] += ldu;
+    ldrun[1] += ldd;
+    if (flg) atomicOr(&c.st->flags, flg);
+    c.st->near_ties += ties;
+  }
+}
+
 template <typename WT>
 __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
   const KArgs& a = *c.a;
@@ -1587,61 +1653,7 @@ __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldru
         c.gb[r * K + cc] = (double)c.G[0][(i0 + r) * np + i0 + cc];
         c.gb[K2 + r * K + cc] = (double)c.G[1][(i0 + r) * np + i0 + cc];
       }
-      if (lane < kb) {
-        c.ublk[lane] = accept_uniform(seed, sweep, l - 1, i0 + lane);
-        c.sblk[lane] = fl[i0 + lane];
-      }
-      wave_sync();
-      int m = 0;
-      double ldu = 0.0, ldd = 0.0;
-      int flg = 0;
-      int64_t ties = 0;
-      for (int ii = 0; ii < kb; ++ii) {
-        const int s = c.sblk[ii];
-        const double u = c.ublk[ii];
-        const double gu = c.gb[ii * K + ii], gd = c.gb[K2 + ii * K + ii];
-        const double du = a.dup[s > 0], dd = a.ddn[s > 0];
-        const double ru = 1.0 + du * (1.0 - gu), rd = 1.0 + dd * (1.0 - gd);
-        const double R = ru * rd;
-        bool ok = true;
-        if (!(fabs(R) < 1e300)) { flg |= FLAG_NONFINITE; ok = false; }
-        else if (R < 0.0) { flg |= FLAG_NEGATIVE; ok = false; }
-        if (ok && fabs(u - R) < 1e-9) ++ties;
-        if (ok && u < R) {
-          const double cu = du / ru, cd = dd / rd;
-          // records x_m (column) and y_m (row) on the block, both spins
-          if (lane < kb) {
-            const int r = lane;
-            c.xb[r * K + m] = -cu * c.gb[r * K + ii];
-            c.xb[K2 + r * K + m] = -cd * c.gb[K2 + r * K + ii];
-            c.yb[m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[ii * K + r];
-            c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
-          }
-          wave_sync();
-          for (int e = lane; e < kb * kb; e += 64) {
-            int r = e / kb, cc = e - r * kb;
-            c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
-            c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
-          }
-          if (lane == 0) {
-            c.site[m] = ii;
-            c.cfu[m] = cu;
-            c.cfd[m] = cd;
-            fl[i0 + ii] = (int8_t)(-s);
-          }
-          ldu += log(fabs(ru));
-          ldd += log(fabs(rd));
-          ++m;
-          wave_sync();
-        }
-      }
-      if (lane == 0) {
-        c.cnt[0] = m;
-        ldrun[0] += ldu;
-        ldrun[1] += ldd;
-        if (flg) atomicOr(&c.st->flags, flg);
-        c.st->near_ties += ties;
-      }
+      decide_block(c, l, i0, kb, seed, sweep, fl, ldrun);
     }
     __syncthreads();
     clk.stop(c.st, PH_DECIDE);
@@ -1757,60 +1769,7 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
           c.gb[K2 + r * K + cc] = (double)c.G[1][(i0 + r) * np + i0 + cc];
         }
       }
-      if (lane < kb) {
-        c.ublk[lane] = accept_uniform(seed, sweep, l - 1, i0 + lane);
-        c.sblk[lane] = fl[i0 + lane];
-      }
-      wave_sync();
-      int m = 0;
-      double ldu = 0.0, ldd = 0.0;
-      int flg = 0;
-      int64_t ties = 0;
-      for (int ii = 0; ii < kb; ++ii) {
-        const int s = c.sblk[ii];
-        const double u = c.ublk[ii];
-        const double gu = c.gb[ii * K + ii], gd = c.gb[K2 + ii * K + ii];
-        const double du = a.dup[s > 0], dd = a.ddn[s > 0];
-        const double ru = 1.0 + du * (1.0 - gu), rd = 1.0 + dd * (1.0 - gd);
-        const double R = ru * rd;
-        bool ok = true;
-        if (!(fabs(R) < 1e300)) { flg |= FLAG_NONFINITE; ok = false; }
-        else if (R < 0.0) { flg |= FLAG_NEGATIVE; ok = false; }
-        if (ok && fabs(u - R) < 1e-9) ++ties;
-        if (ok && u < R) {
-          const double cu = du / ru, cd = dd / rd;
-          if (lane < kb) {
-            const int r = lane;
-            c.xb[r * K + m] = -cu * c.gb[r * K + ii];
-            c.xb[K2 + r * K + m] = -cd * c.gb[K2 + r * K + ii];
-            c.yb[m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[ii * K + r];
-            c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
-          }
-          wave_sync();
-          for (int e = lane; e < kb * kb; e += 64) {
-            int r = e / kb, cc = e - r * kb;
-            c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
-            c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
-          }
-          if (lane == 0) {
-            c.site[m] = ii;
-            c.cfu[m] = cu;
-            c.cfd[m] = cd;
-            fl[i0 + ii] = (int8_t)(-s);
-          }
-          ldu += log(fabs(ru));
-          ldd += log(fabs(rd));
-          ++m;
-          wave_sync();
-        }
-      }
-      if (lane == 0) {
-        c.cnt[0] = m;
-        ldrun[0] += ldu;
-        ldrun[1] += ldd;
-        if (flg) atomicOr(&c.st->flags, flg);
-        c.st->near_ties += ties;
-      }
+      decide_block(c, l, i0, kb, seed, sweep, fl, ldrun);
     }
     __syncthreads();
     clk.stop(c.st, PH_DECIDE);
