@@ -24,6 +24,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The serving leg keeps one stream per resident pool (nine at a time).  HIP maps streams onto
+# GPU_MAX_HW_QUEUES hardware queues per process (4 by default), and pools whose streams share a
+# queue run one after the other.  Ask for at least 16; the legs that use one stream occupy one
+# queue either way.  The runtime reads it when it starts, so it is set before anything else.
+SERVING_HW_QUEUES = 16
+if not os.environ.get("GPU_MAX_HW_QUEUES", "").isdigit() or \
+        int(os.environ["GPU_MAX_HW_QUEUES"]) < SERVING_HW_QUEUES:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(SERVING_HW_QUEUES)
+
 import dqmc_inputs as di  # noqa: E402
 
 PEAK_FP64_MFMA = 78.6e12     # MI355X dense FP64 matrix, FLOP/s
@@ -156,13 +165,21 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
     rq = [Request(d["id"], d["L"], d["beta"], d["sweeps"], d["seed"], d["arrival"] - t_first)
           for d in reqs]
     t0 = time.perf_counter()
-    res = srv.run(rq)
-    wall = time.perf_counter() - t0
+    try:
+        res = srv.run(rq)
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
     st = latency_stats(res)
     span = rq[-1].arrival if len(rq) > 1 else 0.0
+    wait = [r.admitted - r.arrival for r in res]
+    service = [r.finished - r.admitted for r in res]
     return {"rate_req_per_s": rate, "offered_rate_req_per_s": (len(rq) - 1) / span if span > 0 else None,
             "requests": len(res), "p50_s": st["p50_s"], "p99_s": st["p99_s"],
-            "mean_s": st["mean_s"], "updates_per_s": srv.updates / wall, "wall_s": wall,
+            "mean_s": st["mean_s"], "wait_p50_s": float(np.median(wait)) if wait else None,
+            "service_p50_s": float(np.median(service)) if service else None,
+            "hw_queues": GpuExecutor.hw_queues_hint(),
+            "updates_per_s": srv.updates / wall, "wall_s": wall,
             "ticks": srv.ticks, "precision": precision, "lattices_L": list(Ls),
             "pool_capacity": capacity, "tick_sweeps": tick}
 

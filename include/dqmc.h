@@ -180,6 +180,17 @@ dqmc_status dqmc_destroy(dqmc_batch* b);
 
 const char* dqmc_last_error(void);
 
+/* A HIP stream of the caller's own, for batches that run side by side (one resident batch per
+ * model in a serving loop): non-blocking with respect to the null stream, default priority,
+ * on the current device.  The HIP runtime maps streams onto a few hardware queues per process
+ * (GPU_MAX_HW_QUEUES) and kernels of streams that share a queue run one after the other; streams
+ * created together are spread over the queues by the runtime, unlike pooled streams created
+ * earlier for other uses.  out receives the hipStream_t.  dqmc_stream_destroy waits for the
+ * stream's work, then destroys it; the caller first releases everything that still refers to
+ * the stream (events recorded on it, allocator records of host buffers copied on it). */
+dqmc_status dqmc_stream_create(void** out);
+dqmc_status dqmc_stream_destroy(void* stream);
+
 /* Numbers the library chose: site-block size k, stabilisation interval, LDS bytes of the sweep
  * kernel, and the sweep kernel variant (0 = generic with LDS-resident Green's functions,
  * 1 = generic with Green's functions in the workspace, 2 = the N <= 64 register/LDS path). */

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libdqmc.so")
-SOURCES = [os.path.join(HERE, "csrc", "dqmc_abi.hip"), os.path.join(HERE, "csrc", "ising.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dqmc_abi.hip", "ising.hip", "streams.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "dqmc_device.hpp"), os.path.join(ROOT, "include", "dqmc.h"),
            os.path.join(ROOT, "include", "ising.h")]
 

@@ -61,6 +61,8 @@ _SIGS = {
     "dqmc_spin_structure": (_i32, [_vp, _vp, _vp, _vp]),
     "dqmc_destroy": (_i32, [_vp]),
     "dqmc_last_error": (ctypes.c_char_p, []),
+    "dqmc_stream_create": (_i32, [ctypes.POINTER(_vp)]),
+    "dqmc_stream_destroy": (_i32, [_vp]),
     "dqmc_batch_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dqmc_init_slots": (_i32, [_vp, ctypes.POINTER(_i32), _i32, _vp, ctypes.POINTER(_u64), _vp]),
@@ -116,6 +118,23 @@ def _stream(stream, device):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream(device)
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def stream_create(device="cuda:0"):
+    """A non-blocking HIP stream of the caller's own (dqmc_stream_create), not one of torch's
+    pooled streams, as a torch stream object; give it back with stream_destroy."""
+    torch = _torch()
+    h = ctypes.c_void_p()
+    with torch.cuda.device(device):
+        _check(lib().dqmc_stream_create(ctypes.byref(h)))
+    return torch.cuda.ExternalStream(h.value, device=device)
+
+
+def stream_destroy(stream):
+    """Wait for the stream's work and destroy a stream made by stream_create.  Only once nothing
+    that refers to it is alive: torch events recorded on it, and pinned host tensors used in an
+    asynchronous copy on it (torch records an event on that stream when such a tensor is freed)."""
+    _check(lib().dqmc_stream_destroy(ctypes.c_void_p(stream.cuda_stream)))
 
 
 def _ptr(t) -> ctypes.c_void_p:

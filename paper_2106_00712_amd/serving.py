@@ -138,6 +138,18 @@ class Server:
             if self.used_bytes + need <= self.budget:
                 return
 
+    def close(self):
+        """Release every pool (its chains' memory; its stream goes back for reuse); requests
+        still in the pools or the queue are dropped.  A server that is done should be closed:
+        the next server's pools then reuse the same streams, on the same hardware queues, instead
+        of new streams that the runtime may put on queues already in use."""
+        for key in list(self.pools):
+            p = self.pools.pop(key)
+            self.used_bytes -= p.capacity * self.ex.chain_bytes(key)
+            p.running = None
+            self.ex.release_pool(p.handle)
+        self.queue = []
+
     def _admit(self, now: float):
         waiting: List[Request] = []
         grouped: Dict[ModelKey, List[Tuple[int, Request]]] = {}
@@ -232,8 +244,26 @@ def latency_stats(results: Sequence[Result]) -> dict:
             "mean_s": float(lat.mean()), "n": int(lat.size)}
 
 
+# Streams made by dqmc_stream_create, idle, per device.  A released pool hands its stream back
+# here instead of destroying it: torch keeps references to a stream past the pool (a pinned
+# buffer used in an asynchronous copy on it records an event on that stream when it is freed),
+# so the stream must stay valid for the rest of the process.  The next pool reuses it.
+_IDLE_STREAMS: Dict[str, list] = {}
+
+
 class GpuExecutor:
-    """Runs the pools through libdqmc: one Batch per pool, one stream per pool."""
+    """Runs the pools through libdqmc: one Batch per pool, one stream per pool.
+
+    Every device call of a pool goes to that pool's stream, host copies included (a tick's sweep
+    counts come from a pinned host buffer, the observables go back on the pool's stream), and
+    nothing is enqueued on the null stream.  HIP multiplexes streams onto a few hardware queues
+    (GPU_MAX_HW_QUEUES per process, 4 by default): pools whose streams share a queue run one after
+    the other, and a blocking call (slot initialisation, measurement) on one of them waits for the
+    other's whole tick, holding up the host loop meanwhile.  So every pool gets a stream of its
+    own making (dqmc_stream_create), not one of torch's pooled streams, whose queues were handed
+    out when torch created them; the pools then run side by side when the process has at least
+    as many hardware queues as pools.  Streams are reused, never destroyed (see _IDLE_STREAMS).
+    `hw_queues_hint` says how many hardware queues the runtime was asked for."""
 
     def __init__(self, hopping: Callable[[int], np.ndarray], t=1.0, U=4.0, dtau=0.1, stab_every=10,
                  refresh_every=0, delay_rank=0, device="cuda:0"):
@@ -245,6 +275,15 @@ class GpuExecutor:
         self.stab, self.refresh, self.delay = stab_every, refresh_every, delay_rank
         self.device = torch.device(device)
         self._models = {}
+
+    @staticmethod
+    def hw_queues_hint() -> int:
+        """Hardware queues per process that the HIP runtime was configured with (its default 4)."""
+        import os
+        try:
+            return int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        except ValueError:
+            return 4
 
     def n_slices(self, key: ModelKey) -> int:
         return int(round(key[1] / self.dtau))
@@ -266,12 +305,20 @@ class GpuExecutor:
         torch = self.torch
         seeds = np.arange(capacity, dtype=np.uint64) + (np.uint64(0xD0C0) << np.uint64(40))
         b = self.dq.Batch(self.model(key), seeds, device=self.device)
-        return {"batch": b, "stream": torch.cuda.Stream(device=self.device),
+        idle = _IDLE_STREAMS.setdefault(str(self.device), [])
+        stream = idle.pop() if idle else self.dq.stream_create(self.device)
+        pool = {"batch": b, "stream": stream,
                 "counts": torch.zeros(capacity, dtype=torch.int32, device=self.device),
+                "counts_host": torch.zeros(capacity, dtype=torch.int32, pin_memory=True),
                 "done": torch.cuda.Event()}
+        # the batch's set-up ran on the current stream: finish it before the pool's stream is used
+        torch.cuda.synchronize(self.device)
+        return pool
 
     def release_pool(self, pool):
+        pool["stream"].synchronize()
         pool["batch"].close()
+        _IDLE_STREAMS.setdefault(str(self.device), []).append(pool["stream"])
 
     def init_slots(self, pool, slots, reqs):
         torch = self.torch
@@ -286,11 +333,12 @@ class GpuExecutor:
             b.init_slots(slots, seeds, fields, stream=pool["stream"])
 
     def launch_tick(self, pool, counts):
+        # the pinned buffer's previous copy has finished: the pool's last tick is done
         torch = self.torch
         s = pool["stream"]
-        s.wait_stream(torch.cuda.current_stream(self.device))
+        pool["counts_host"].numpy()[:] = counts
         with torch.cuda.stream(s):
-            pool["counts"].copy_(torch.from_numpy(counts), non_blocking=False)
+            pool["counts"].copy_(pool["counts_host"], non_blocking=True)
             pool["batch"].sweep_counts(pool["counts"], stream=s)
             pool["done"].record(s)
 
@@ -304,11 +352,13 @@ class GpuExecutor:
             time.sleep(2e-4)
 
     def measure(self, pool, slots, keep_fields):
+        torch = self.torch
         b = pool["batch"]
-        obs = b.measure(stream=pool["stream"])
-        fields = None
-        if keep_fields:
-            fields = b.fields(stream=pool["stream"]).cpu().numpy()[list(slots)]
+        with torch.cuda.stream(pool["stream"]):
+            obs = b.measure(stream=pool["stream"])
+            fields = None
+            if keep_fields:
+                fields = b.fields(stream=pool["stream"]).cpu().numpy()[list(slots)]
         return obs[list(slots)], fields
 
     def advance(self, dt):

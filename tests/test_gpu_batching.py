@@ -117,7 +117,10 @@ def _serve(dq, reqs, capacity, tick, precision="fp64"):
                      refresh_every=4 if precision == "fp32_wrap" else 0)
     srv = Server(ex, hbm_budget=8 << 30, tick_sweeps=tick, pool_capacity=capacity,
                  precision=precision, keep_fields=True)
-    return srv.run(reqs, realtime=False)
+    try:
+        return srv.run(reqs, realtime=False)
+    finally:
+        srv.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_wrap"])

@@ -101,6 +101,14 @@ def test_budget_is_respected_and_idle_pools_are_released():
     assert srv.used_bytes <= budget
 
 
+def test_close_releases_every_pool():
+    reqs = poisson_requests(30, rate=500.0, seed=3)
+    ex, srv, res = _serve(reqs, hbm_budget=10 ** 9, tick_sweeps=5, pool_capacity=4)
+    assert len(res) == 30 and ex.live_bytes > 0
+    srv.close()
+    assert ex.live_bytes == 0 and srv.used_bytes == 0 and not srv.pools and srv.pending() == 0
+
+
 def test_request_takes_a_freed_slot_while_others_run():
     # capacity 2: A (long) and B (short) start together; C arrives later and must start in B's
     # slot before A has finished
