@@ -18,9 +18,16 @@
 
 #include "philox.hpp"
 
-// Pointer into LDS (address space 3), for arguments of functions that are not inlined.
+// Pointer into LDS (address space 3), for arguments of functions that are not inlined and for
+// LDS areas reached through generic pointers.
 #ifndef DQMC_LDS
 #define DQMC_LDS __attribute__((address_space(3)))
+#endif
+// Pointer into global memory (address space 1): loads through it are global loads, counted by
+// vmcnt alone, where loads through generic pointers are flat loads that also hold lgkmcnt (so a
+// wait for LDS reads would wait for them too).
+#ifndef DQMC_GLB
+#define DQMC_GLB __attribute__((address_space(1)))
 #endif
 
 namespace dqmc {
@@ -149,7 +156,9 @@ __device__ __forceinline__ void wg_gemm(int nb, int M, int Nc, int K, const T* A
 // Matrix products for chains whose matrices live in the chain's workspace (N > 64): operands
 // are read from HBM/L2 in coalesced 16-wide K panels, staged through a double-buffered LDS
 // area, and multiplied on the matrix cores in 64 x 64 output macro-tiles (each wavefront a
-// 32 x 32 quadrant of 2 x 2 MFMA tiles).
+// 32 x 32 quadrant of 2 x 2 MFMA tiles).  The operands are read as global memory and the
+// staging area as LDS, so the loads of the next panel stay in flight while the current one is
+// multiplied (vmcnt and lgkmcnt are waited on separately).
 constexpr int TG_M = 64;    // macro-tile rows / columns
 constexpr int TG_K = 16;    // K panel
 // LDS staging in doubles: two buffers of A (K-major, TG_K x TG_M) and B (TG_K x TG_M)
@@ -157,17 +166,24 @@ constexpr int TG_STAGE_DOUBLES = 4 * TG_K * TG_M;
 
 // C_b(i, j) = sum_{k < K} A_b(i, k) B_b(k, j) for b < nb, i < M, j < Nc (M, Nc multiples of 16),
 // A_b(i, k) = A_b[i sai + k sak], B_b(k, j) = B_b[k sbk + j sbj] with unit stride in one of
-// each pair (row- or column-major operands).  epi(b, i, j, value) is called once per output
-// element by the lane that owns it.  All NT threads of the workgroup take part.
+// each pair (row- or column-major operands).  The operands must be in global memory (the
+// chain's workspace or the model constants), never in LDS.  epi(b, i, j, value) is called once
+// per output element by the lane that owns it.  All NT threads of the workgroup take part.
 template <typename T, typename Epi>
-__device__ __forceinline__ void gemm_tiled(double* stage, int nb, int M, int Nc, int K, const T* A0, const T* A1,
-                           int sai, int sak, const T* B0, const T* B1, int sbk, int sbj, Epi epi) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void gemm_tiled(DQMC_LDS double* stage, int nb, int M, int Nc, int K,
+                                           const T* A0g, const T* A1g, int sai, int sak,
+                                           const T* B0g, const T* B1g, int sbk, int sbj, Epi epi) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches below
   const int li = lane & 15, lk = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
   const int mt = (M + TG_M - 1) / TG_M, nt = (Nc + TG_M - 1) / TG_M, kc = (K + TG_K - 1) / TG_K;
-  T* As[2] = {(T*)stage, (T*)stage + TG_K * TG_M};
-  T* Bs[2] = {(T*)stage + 2 * TG_K * TG_M, (T*)stage + 3 * TG_K * TG_M};
+  const DQMC_GLB T* A0 = (const DQMC_GLB T*)A0g;
+  const DQMC_GLB T* A1 = (const DQMC_GLB T*)A1g;
+  const DQMC_GLB T* B0 = (const DQMC_GLB T*)B0g;
+  const DQMC_GLB T* B1 = (const DQMC_GLB T*)B1g;
+  DQMC_LDS T* As[2] = {(DQMC_LDS T*)stage, (DQMC_LDS T*)stage + TG_K * TG_M};
+  DQMC_LDS T* Bs[2] = {(DQMC_LDS T*)stage + 2 * TG_K * TG_M, (DQMC_LDS T*)stage + 3 * TG_K * TG_M};
   const bool a_rows = (sak == 1);    // A contiguous along k (row-major), else along i
   const bool b_rows = (sbj == 1);    // B contiguous along j (row-major), else along k
   // each thread moves 4 consecutive elements of each panel per chunk
@@ -176,8 +192,8 @@ __device__ __forceinline__ void gemm_tiled(double* stage, int nb, int M, int Nc,
   for (int t = 0; t < nb * mt * nt; ++t) {
     const int b = t / (mt * nt), tt = t - b * (mt * nt);
     const int m0 = (tt / nt) * TG_M, n0 = (tt - (tt / nt) * nt) * TG_M;
-    const T* A = b ? A1 : A0;
-    const T* B = b ? B1 : B0;
+    const DQMC_GLB T* A = b ? A1 : A0;
+    const DQMC_GLB T* B = b ? B1 : B0;
     T ra[4], rb[4];
     auto load = [&](int k0) {
 #pragma unroll
@@ -422,7 +438,8 @@ template <typename T, typename WT, typename Epi>
 __device__ __forceinline__ void ctx_gemm(Ctx<WT>& c, int nb, int M, int Nc, int K, const T* A0,
                                          const T* A1, int sai, int sak, const T* B0, const T* B1,
                                          int sbk, int sbj, Epi epi) {
-  if (c.stage) gemm_tiled<T>(c.stage, nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
+  if (c.stage)
+    gemm_tiled<T>((DQMC_LDS double*)c.stage, nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
   else wg_gemm<T>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
 }
 
@@ -779,7 +796,7 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
                                          DQMC_LDS double* dtmp, double* X, double* A, double* Ud,
                                          double* dd, int* flags) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* stage = (double*)stage_lds;
+  DQMC_LDS double* stage = stage_lds;
   double* V = qrv;                         // reflectors, np x np column-major, zero above the diagonal
   double* Tg = qrv + (size_t)np * np;      // T of panel p at Tg[p QB^2], row-major
   DQMC_LDS double* red = stage_lds;        // [NW][QB] partial sums
@@ -1009,7 +1026,7 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
                                             const DQMC_LDS double* bt, const double* X, double* W,
                                             double* Ud) {
   const int tid = threadIdx.x;
-  double* stage = (double*)stage_lds;
+  DQMC_LDS double* stage = stage_lds;
   double* V = qrv;
   double* Tg = qrv + (size_t)np * np;
   for (int e = tid; e < np * np; e += NT) {
@@ -1249,7 +1266,7 @@ __device__ __noinline__ double gj_blocked(int n, int np, DQMC_LDS double* stage_
                                           const DQMC_LDS double* rs, double* M, double* Z,
                                           double* dst) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* stage = (double*)stage_lds;
+  DQMC_LDS double* stage = stage_lds;
   DQMC_LDS double* red = stage_lds;                     // [NW] argmax keys
   DQMC_LDS int* redi = (DQMC_LDS int*)(red + NW);       // [NW] argmax rows
   DQMC_LDS double* prow = red + 2 * NW;                 // [QB] pivot row, panel part
