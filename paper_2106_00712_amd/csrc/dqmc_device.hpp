@@ -573,14 +573,17 @@ __device__ __forceinline__ void wg_qrp(Ctx<WT>& c, double* X) {
 
 // wg_qrp for matrices in the workspace (np <= 64 CR): the same steps, pivots and per-lane
 // summation order (so the same bits), with each column's active part held in registers between
-// its dot product and its update instead of being read twice, and two columns per wavefront in
-// flight so that their memory latencies overlap.  vb: the pivot column (LDS, np doubles).
+// its dot product and its update instead of being read twice, and QC columns per wavefront in
+// flight so that their memory latencies overlap.  X is read and written as global memory (the
+// waits for the LDS vectors then do not wait for it).  vb: the pivot column (LDS, np doubles).
+constexpr int QC = 4;   // columns per wavefront per step of the trailing update
 template <int CR>
-__device__ __noinline__ void qrp_columns(int n, int np, double* X, DQMC_LDS double* nrm,
+__device__ __noinline__ void qrp_columns(int n, int np, double* Xg, DQMC_LDS double* nrm,
                                          DQMC_LDS int* rank, DQMC_LDS int* ordv, DQMC_LDS double* vb,
                                          DQMC_LDS double* vd, DQMC_LDS double* bt,
                                          DQMC_LDS double* redv, DQMC_LDS int* redi) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  DQMC_GLB double* X = (DQMC_GLB double*)Xg;
   for (int k = tid; k < n; k += NT) rank[k] = -1;
   for (int col = wave; col < n; col += NW) {
     double s = 0;
@@ -623,7 +626,7 @@ __device__ __noinline__ void qrp_columns(int n, int np, double* X, DQMC_LDS doub
       }
     }
     p = (p >= 0 && p < n) ? p : j;
-    const double* xp = X + (size_t)p * np;
+    const DQMC_GLB double* xp = X + (size_t)p * np;
     const double xj = xp[j];
     const double nx = sqrt(nrm[p]);
     const double alpha = (xj >= 0.0) ? -nx : nx;
@@ -632,46 +635,63 @@ __device__ __noinline__ void qrp_columns(int n, int np, double* X, DQMC_LDS doub
     for (int r = j + tid; r < n; r += NT) vb[r] = (r == j) ? v0 : xp[r];
     if (tid == 0) { rank[p] = j; ordv[j] = p; }
     __syncthreads();
-    for (int col = wave; col < n; col += 2 * NW) {
-      const int cb = col + NW;
-      const bool ua = (col != p) && rank[col] < 0;
-      const bool ub = (cb < n) && (cb != p) && rank[cb] < 0;
-      if (!ua && !ub) continue;
-      double* xa = X + (size_t)col * np;
-      double* xb = X + (size_t)(ub ? cb : col) * np;
-      double ra[CR], rb[CR];
+    // trailing columns col0 + q NW (q < QC) of this wavefront: y = x - beta (v^T x) v
+    for (int col0 = wave; col0 < n; col0 += QC * NW) {
+      bool use[QC];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < QC; ++q) {
+        const int cq = col0 + q * NW;
+        use[q] = (cq < n) && (cq != p) && rank[cq] < 0;
+        any = any || use[q];
+      }
+      if (!any) continue;
+      DQMC_GLB double* xq[QC];
+#pragma unroll
+      for (int q = 0; q < QC; ++q) xq[q] = X + (size_t)(use[q] ? col0 + q * NW : col0) * np;
+      double rq[QC][CR];
 #pragma unroll
       for (int t = 0; t < CR; ++t) {
         const int r = j + lane + 64 * t;
-        ra[t] = (ua && r < n) ? xa[r] : 0.0;
-        rb[t] = (ub && r < n) ? xb[r] : 0.0;
+#pragma unroll
+        for (int q = 0; q < QC; ++q) rq[q][t] = (use[q] && r < n) ? xq[q][r] : 0.0;
       }
-      double wa = 0, wb = 0;
+      double w[QC];
+#pragma unroll
+      for (int q = 0; q < QC; ++q) w[q] = 0.0;
 #pragma unroll
       for (int t = 0; t < CR; ++t) {
         const int r = j + lane + 64 * t;
         if (r < n) {
-          wa += vb[r] * ra[t];
-          wb += vb[r] * rb[t];
+#pragma unroll
+          for (int q = 0; q < QC; ++q) w[q] += vb[r] * rq[q][t];
         }
       }
-      if (ua) wa = wave_sum_dpp(wa) * beta;
-      if (ub) wb = wave_sum_dpp(wb) * beta;
-      double sa = 0, sb = 0;
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+        if (use[q]) w[q] = wave_sum_dpp(w[q]) * beta;
+      double sq[QC];
+#pragma unroll
+      for (int q = 0; q < QC; ++q) sq[q] = 0.0;
 #pragma unroll
       for (int t = 0; t < CR; ++t) {
         const int r = j + lane + 64 * t;
         if (r < n) {
           const double v = vb[r];
-          const double ya = ra[t] - wa * v;
-          const double yb = rb[t] - wb * v;
-          if (ua) xa[r] = ya;
-          if (ub) xb[r] = yb;
-          if (r > j) { sa += ya * ya; sb += yb * yb; }
+#pragma unroll
+          for (int q = 0; q < QC; ++q) {
+            const double y = rq[q][t] - w[q] * v;
+            if (use[q]) xq[q][r] = y;
+            if (r > j) sq[q] += y * y;
+          }
         }
       }
-      if (ua) { sa = wave_sum_dpp(sa); if (lane == 0) nrm[col] = sa; }
-      if (ub) { sb = wave_sum_dpp(sb); if (lane == 0) nrm[cb] = sb; }
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+        if (use[q]) {
+          const double sn = wave_sum_dpp(sq[q]);
+          if (lane == 0) nrm[col0 + q * NW] = sn;
+        }
     }
     alpha_prev = alpha; v0_prev = v0; beta_prev = beta; p_prev = p;
     __syncthreads();
