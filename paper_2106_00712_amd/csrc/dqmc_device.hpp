@@ -576,7 +576,7 @@ __device__ __forceinline__ void wg_qrp(Ctx<WT>& c, double* X) {
 // its dot product and its update instead of being read twice, and QC columns per wavefront in
 // flight so that their memory latencies overlap.  X is read and written as global memory (the
 // waits for the LDS vectors then do not wait for it).  vb: the pivot column (LDS, np doubles).
-constexpr int QC = 4;   // columns per wavefront per step of the trailing update
+constexpr int QC = 8;   // columns per wavefront per step of the trailing update
 template <int CR>
 __device__ __noinline__ void qrp_columns(int n, int np, double* Xg, DQMC_LDS double* nrm,
                                          DQMC_LDS int* rank, DQMC_LDS int* ordv, DQMC_LDS double* vb,
