@@ -411,6 +411,8 @@ def main():
     ap.add_argument("--workload", default=None,
                     help="only a throughput line for this workload (e.g. square20x20_U8_b10)")
     ap.add_argument("--chains", type=int, default=0, help="with --workload: number of chains")
+    ap.add_argument("--stab", type=int, default=0,
+                    help="with --workload: stabilisation interval in slices (0: the workload's)")
     ap.add_argument("--precision", default="fp64", help="with --workload: fp64 or fp32_wrap")
     ap.add_argument("--mixed", action="store_true",
                     help="only the mixed-size batch: honeycomb 6x6 + 12x12, FP32 wraps, one graph")
@@ -436,9 +438,9 @@ def main():
 
     if args.workload:
         wl = di.WORKLOADS[args.workload]
-        if args.chains:
+        if args.chains or args.stab:
             wl = di.Workload(wl.name, wl.config_id, wl.lattice, wl.L, wl.U, wl.beta, wl.dtau,
-                             args.chains, wl.n_sweeps, wl.stab_every)
+                             args.chains or wl.n_chains, wl.n_sweeps, args.stab or wl.stab_every)
         qb = choose_qr(wl, args.qr)
         r = run_gpu(wl, args.precision, args.steps, args.warmup, args.delay_rank,
                     (args.refresh or 10) if args.precision == "fp32_wrap" else 0, qr_blocked=qb,
@@ -459,6 +461,7 @@ def main():
                           "max_drift": float(o["max_drift"].max()),
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),
+                          "flagged_chains": int(np.count_nonzero(o["flags"])),
                           "phase_share": r["phase_share"]}))
         return
     if args.ising:
