@@ -184,6 +184,46 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
             "pool_capacity": capacity, "tick_sweeps": tick}
 
 
+def run_serving_models(precision: str = "fp64", sweeps_small: int = 10, sweeps_large: int = 2):
+    """Compute time of one request of every model of the serving workload, alone on the GPU: one
+    chain per model (one workgroup, so one CU), ms per sweep from HIP events.  The request
+    latency without queueing is sweeps x ms per sweep; since L, beta and the sweep count are
+    drawn uniformly and independently, its distribution over the whole request mix follows
+    exactly from the per-model times."""
+    import torch
+    from paper_2106_00712_amd import dqmc
+    models = []
+    for L in di.SERVING_L:
+        for beta in di.SERVING_BETA:
+            n_sl = int(round(beta / 0.1))
+            m = dqmc.make_model(di.square_hopping(L), 4.0, 0.1, n_sl, 10, precision=precision,
+                                refresh_every=3 if precision == "fp32_wrap" else 0)
+            b = dqmc.Batch(m, np.array([(4 << 32) | 7], dtype=np.uint64))
+            b.sweep(1)
+            k = sweeps_small if L <= 8 else sweeps_large
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            b.sweep(k)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / k
+            o = b.measure()
+            models.append({"L": L, "beta": beta, "n_sites": L * L, "n_slices": n_sl, "variant": b.variant,
+                           "ms_per_sweep": ms, "flags": int(o["flags"][0])})
+            print(f"serving model L={L} beta={beta} {precision}: {ms:.2f} ms per sweep", file=sys.stderr,
+                  flush=True)
+            b.close()
+    lo, hi = di.SERVING_SWEEPS
+    sweeps = np.arange(lo, hi + 1)
+    lat = np.sort(np.concatenate([sweeps * m["ms_per_sweep"] * 1e-3 for m in models]))
+    q = lambda f: float(lat[min(len(lat) - 1, int(np.ceil(f * len(lat))) - 1)])
+    return {"precision": precision, "models": models,
+            "request_latency_without_queueing_s": {"p50": q(0.5), "p99": q(0.99), "mean": float(lat.mean()),
+                                                    "max": float(lat[-1])},
+            "note": "one chain alone per model; L, beta, sweeps uniform over the serving workload"}
+
+
 def run_mixed(steps: int, refresh: int, n_each: int, qr_mode: str = "auto", sweep_mode: int = 0):
     """Honeycomb 6x6 (N = 72) and 12x12 (N = 288) chains side by side in one recorded graph,
     FP32 wraps with FP64 refresh every `refresh` slices, against the same batches in FP64."""
@@ -408,6 +448,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
                     help="only the serving workload over every lattice size (minutes per rate)")
+    ap.add_argument("--serving-models", action="store_true",
+                    help="compute time of one request of every serving model (L up to 16), alone")
     ap.add_argument("--workload", default=None,
                     help="only a throughput line for this workload (e.g. square20x20_U8_b10)")
     ap.add_argument("--chains", type=int, default=0, help="with --workload: number of chains")
@@ -476,6 +518,9 @@ def main():
     if args.mixed:
         print(json.dumps(run_mixed(args.steps, args.refresh or 10, args.chains or 256, args.qr,
                                    args.sweep_mode)))
+        return
+    if args.serving_models:
+        print(json.dumps({"serving_models": [run_serving_models("fp64"), run_serving_models("fp32_wrap")]}))
         return
     if args.serving_full:
         out = [run_serving(rate, 48, di.SERVING_L, "fp64", 16, 10, 0) for rate in (50, 2000)]
