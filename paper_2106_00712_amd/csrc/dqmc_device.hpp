@@ -1670,6 +1670,42 @@ __device__ __forceinline__ void decide_block(Ctx<WT>& c, int l, int i0, int kb, 
   }
 }
 
+// Sherman-Morrison vectors of a block's m accepted flips (sites j_t = i0 + site[t], t < m <=
+// SM_KMAX, the largest delay rank of the generic kernels), at one row r of X or column r of Y:
+//   x_t = -cf_t (g_t + sum_{t2 < t} x_t2 yb[t2][j_t]),       g_t = G(r, j_t)
+//   y_t = [r = j_t] - g_t - sum_{t2 < t} xb[j_t][t2] y_t2,   g_t = G(j_t, r)   (0 for r >= n)
+// v holds g_t on entry and the vector on exit.  The loops are unrolled to SM_KMAX so that v stays
+// in registers (a run-time-indexed array would live in scratch memory) and the caller's loads of
+// g are all in flight together; the operations and their order are those of the plain loops.
+constexpr int SM_KMAX = 32;
+__device__ __forceinline__ void sm_vec_x(int m, const int* site, const double* cf, const double* ybs,
+                                         int K, double (&v)[SM_KMAX]) {
+#pragma unroll
+  for (int t = 0; t < SM_KMAX; ++t) {
+    if (t < m) {
+      const int jt = site[t];
+      double acc = v[t];
+#pragma unroll
+      for (int t2 = 0; t2 < t; ++t2) acc += v[t2] * ybs[t2 * K + jt];
+      v[t] = -cf[t] * acc;
+    }
+  }
+}
+__device__ __forceinline__ void sm_vec_y(int m, int r, int i0, int n, const int* site,
+                                         const double* xbs, int K, double (&v)[SM_KMAX]) {
+#pragma unroll
+  for (int t = 0; t < SM_KMAX; ++t) {
+    if (t < m) {
+      const int jt = site[t];
+      double acc = ((r == i0 + jt) ? 1.0 : 0.0) - v[t];
+#pragma unroll
+      for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * K + t2] * v[t2];
+      if (r >= n) acc = 0.0;
+      v[t] = acc;
+    }
+  }
+}
+
 template <typename WT>
 __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldrun) {
   const KArgs& a = *c.a;
@@ -1712,29 +1748,19 @@ __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldru
         const double* cf = sp ? c.cfd : c.cfu;
         const double* xbs = c.xb + sp * K2;
         const double* ybs = c.yb + sp * K2;
-        double tmp[64];
-        if (kind == 0) {
-          WT* X = sp ? X1 : X0;
-          for (int t = 0; t < m; ++t) {
-            const int jt = c.site[t];
-            double acc = (r < n) ? (double)G0[r * np + i0 + jt] : 0.0;
-            for (int t2 = 0; t2 < t; ++t2) acc += tmp[t2] * ybs[t2 * K + jt];
-            tmp[t] = -cf[t] * acc;
-            X[t * np + r] = (WT)tmp[t];
-          }
-          for (int t = m; t < mp; ++t) X[t * np + r] = (WT)0;
-        } else {
-          WT* Y = sp ? Y1 : Y0;
-          for (int t = 0; t < m; ++t) {
-            const int jt = c.site[t];
-            double acc = ((r == i0 + jt) ? 1.0 : 0.0) - ((r < n) ? (double)G0[(i0 + jt) * np + r] : 0.0);
-            for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * K + t2] * tmp[t2];
-            if (r >= n) acc = 0.0;
-            tmp[t] = acc;
-            Y[t * np + r] = (WT)acc;
-          }
-          for (int t = m; t < mp; ++t) Y[t * np + r] = (WT)0;
+        double v[SM_KMAX];
+#pragma unroll
+        for (int t = 0; t < SM_KMAX; ++t) {
+          v[t] = 0.0;
+          if (t < m && r < n)
+            v[t] = (double)(kind == 0 ? G0[r * np + i0 + c.site[t]] : G0[(i0 + c.site[t]) * np + r]);
         }
+        if (kind == 0) sm_vec_x(m, c.site, cf, ybs, K, v);
+        else sm_vec_y(m, r, i0, n, c.site, xbs, K, v);
+        WT* P = kind == 0 ? (sp ? X1 : X0) : (sp ? Y1 : Y0);
+#pragma unroll
+        for (int t = 0; t < SM_KMAX; ++t)
+          if (t < mp) P[t * np + r] = (t < m) ? (WT)v[t] : (WT)0;
       }
     }
     __syncthreads();
@@ -1847,32 +1873,23 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
         const double* cf = sp ? c.cfd : c.cfu;
         const double* xbs = c.xb + sp * K2;
         const double* ybs = c.yb + sp * K2;
-        double tmp[64];
-        if (kind == 0) {
-          WT* X = XA[sp] + (size_t)mA * np;
-          for (int t = 0; t < m; ++t) {
-            const int jt = c.site[t];
-            double acc = 0.0;
-            if (r < n) acc = mA ? (double)Cc[sp][(size_t)t * np + r] : (double)G0[r * np + i0 + jt];
-            for (int t2 = 0; t2 < t; ++t2) acc += tmp[t2] * ybs[t2 * K + jt];
-            tmp[t] = -cf[t] * acc;
-            X[(size_t)t * np + r] = (WT)tmp[t];
+        double v[SM_KMAX];
+#pragma unroll
+        for (int t = 0; t < SM_KMAX; ++t) {
+          v[t] = 0.0;
+          if (t < m && r < n) {
+            if (kind == 0)
+              v[t] = mA ? (double)Cc[sp][(size_t)t * np + r] : (double)G0[r * np + i0 + c.site[t]];
+            else
+              v[t] = mA ? (double)Rw[sp][(size_t)t * np + r] : (double)G0[(i0 + c.site[t]) * np + r];
           }
-          for (int t = m; t < mp; ++t) X[(size_t)t * np + r] = (WT)0;
-        } else {
-          WT* Y = YA[sp] + (size_t)mA * np;
-          for (int t = 0; t < m; ++t) {
-            const int jt = c.site[t];
-            double g = 0.0;
-            if (r < n) g = mA ? (double)Rw[sp][(size_t)t * np + r] : (double)G0[(i0 + jt) * np + r];
-            double acc = ((r == i0 + jt) ? 1.0 : 0.0) - g;
-            for (int t2 = 0; t2 < t; ++t2) acc -= xbs[jt * K + t2] * tmp[t2];
-            if (r >= n) acc = 0.0;
-            tmp[t] = acc;
-            Y[(size_t)t * np + r] = (WT)acc;
-          }
-          for (int t = m; t < mp; ++t) Y[(size_t)t * np + r] = (WT)0;
         }
+        if (kind == 0) sm_vec_x(m, c.site, cf, ybs, K, v);
+        else sm_vec_y(m, r, i0, n, c.site, xbs, K, v);
+        WT* P = (kind == 0 ? XA[sp] : YA[sp]) + (size_t)mA * np;
+#pragma unroll
+        for (int t = 0; t < SM_KMAX; ++t)
+          if (t < mp) P[(size_t)t * np + r] = (t < m) ? (WT)v[t] : (WT)0;
       }
       __syncthreads();
       clk.stop(c.st, PH_PANEL);
