@@ -251,6 +251,71 @@ __device__ __forceinline__ void gemm_tiled(DQMC_LDS double* stage, int nb, int M
   }
 }
 
+// Thin products of the workspace kernels (one output side <= 32, contraction <= a few hundred):
+// each wavefront computes whole 32 x 32 output tiles on its own, reading its operands straight
+// from global memory with WK_U k-steps of 4 in flight per lane (no LDS staging, no workgroup
+// barrier), where gemm_tiled would give one 64 x 64 tile, half of it idle, to the whole
+// workgroup panel by panel.  The MFMAs see the same inputs in the same k order as in gemm_tiled
+// and wg_gemm (steps of 4 ascending), so the results are the same bits.  Same contract as
+// gemm_tiled: operands in global memory, M and Nc multiples of 16, K a multiple of 4; epi is
+// called once per output element by the lane that owns it.
+constexpr int WK_U = 8;
+template <typename T, typename Epi>
+__device__ __forceinline__ void wave_gemm(int nb, int M, int Nc, int K, const T* A0g, const T* A1g,
+                                          int sai, int sak, const T* B0g, const T* B1g, int sbk,
+                                          int sbj, Epi epi) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt = (M + 31) >> 5, nt = (Nc + 31) >> 5;
+  const DQMC_GLB T* A0 = (const DQMC_GLB T*)A0g;
+  const DQMC_GLB T* A1 = (const DQMC_GLB T*)A1g;
+  const DQMC_GLB T* B0 = (const DQMC_GLB T*)B0g;
+  const DQMC_GLB T* B1 = (const DQMC_GLB T*)B1g;
+  for (int t = wave; t < nb * mt * nt; t += NW) {
+    const int b = t / (mt * nt), tt = t - b * (mt * nt);
+    const int i0 = (tt / nt) * 32, j0 = (tt - (tt / nt) * nt) * 32;
+    const DQMC_GLB T* A = b ? A1 : A0;
+    const DQMC_GLB T* B = b ? B1 : B0;
+    const int ia = i0 + li, ib = i0 + 16 + li, ja = j0 + li, jb = j0 + 16 + li;
+    const bool va = ia < M, vb = ib < M, wa = ja < Nc, wb = jb < Nc;
+    typename acc4<T>::type acc[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[r][q] = typename acc4<T>::type{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4 * WK_U) {
+      T a[WK_U][2], bv[WK_U][2];
+#pragma unroll
+      for (int s2 = 0; s2 < WK_U; ++s2) {
+        const int k = k0 + 4 * s2 + lk;
+        const bool kv = k < K;
+        a[s2][0] = (kv && va) ? A[(size_t)ia * sai + (size_t)k * sak] : (T)0;
+        a[s2][1] = (kv && vb) ? A[(size_t)ib * sai + (size_t)k * sak] : (T)0;
+        bv[s2][0] = (kv && wa) ? B[(size_t)k * sbk + (size_t)ja * sbj] : (T)0;
+        bv[s2][1] = (kv && wb) ? B[(size_t)k * sbk + (size_t)jb * sbj] : (T)0;
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < WK_U; ++s2) {
+        if (k0 + 4 * s2 < K) {
+          acc[0][0] = mfma(a[s2][0], bv[s2][0], acc[0][0]);
+          if (wb) acc[0][1] = mfma(a[s2][0], bv[s2][1], acc[0][1]);
+          if (vb) acc[1][0] = mfma(a[s2][1], bv[s2][0], acc[1][0]);
+          if (vb && wb) acc[1][1] = mfma(a[s2][1], bv[s2][1], acc[1][1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (i0 + 16 * r >= M || j0 + 16 * q >= Nc) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) epi(b, i0 + 16 * r + out_row<T>(v, lane), j0 + 16 * q + li, acc[r][q][v]);
+      }
+  }
+}
+
 // ------------------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
@@ -1817,7 +1882,7 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
     // ---- the block of the true G
     if (mA > 0) {
       const int kr = (kb + 15) & ~15;
-      wg_gemm<WT>(2, kr, kr, mA, XA[0] + i0, XA[1] + i0, 1, np, YA[0] + i0, YA[1] + i0, np, 1,
+      wave_gemm<WT>(2, kr, kr, mA, XA[0] + i0, XA[1] + i0, 1, np, YA[0] + i0, YA[1] + i0, np, 1,
                   [&](int b, int i, int j, WT v) {
                     if (i < kb && j < kb)
                       c.gb[b * K2 + i * K + j] = (double)c.G[b][(i0 + i) * np + i0 + j] + (double)v;
@@ -1850,13 +1915,13 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
           Xs[b][t * KT + u] = (col >= 0) ? XA[b][(size_t)u * np + col] : (WT)0;
         }
         __syncthreads();
-        ctx_gemm<WT>(c, 2, np, mr, mA, XA[0], XA[1], 1, np, Ys[0], Ys[1], K16, 1,
+        wave_gemm<WT>(2, np, mr, mA, XA[0], XA[1], 1, np, Ys[0], Ys[1], K16, 1,
                      [&](int b, int i, int j, WT v) {
                        if (j < m)
                          Cc[b][(size_t)j * np + i] =
                              (WT)(((i < n) ? (double)c.G[b][i * np + i0 + c.site[j]] : 0.0) + (double)v);
                      });
-        ctx_gemm<WT>(c, 2, mr, np, mA, Xs[0], Xs[1], KT, 1, YA[0], YA[1], np, 1,
+        wave_gemm<WT>(2, mr, np, mA, Xs[0], Xs[1], KT, 1, YA[0], YA[1], np, 1,
                      [&](int b, int i, int j, WT v) {
                        if (i < m)
                          Rw[b][(size_t)i * np + j] =
