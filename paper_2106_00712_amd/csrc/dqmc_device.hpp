@@ -259,11 +259,13 @@ __device__ __forceinline__ void gemm_tiled(DQMC_LDS double* stage, int nb, int M
 // and wg_gemm (steps of 4 ascending), so the results are the same bits.  Same contract as
 // gemm_tiled: operands in global memory, M and Nc multiples of 16, K a multiple of 4; epi is
 // called once per output element by the lane that owns it.
+// ADD: C_b[i ldc + j] += (A_b B_b)(i, j) instead of epi, with the tile of C loaded together with
+// the first operands (no memory round trip after the products).
 constexpr int WK_U = 8;
-template <typename T, typename Epi>
-__device__ __forceinline__ void wave_gemm(int nb, int M, int Nc, int K, const T* A0g, const T* A1g,
-                                          int sai, int sak, const T* B0g, const T* B1g, int sbk,
-                                          int sbj, Epi epi) {
+template <typename T, bool ADD, typename Epi>
+__device__ __forceinline__ void wave_gemm_impl(int nb, int M, int Nc, int K, const T* A0g, const T* A1g,
+                                               int sai, int sak, const T* B0g, const T* B1g, int sbk,
+                                               int sbj, T* C0g, T* C1g, int ldc, Epi epi) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -284,6 +286,19 @@ __device__ __forceinline__ void wave_gemm(int nb, int M, int Nc, int K, const T*
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int q = 0; q < 2; ++q) acc[r][q] = typename acc4<T>::type{0, 0, 0, 0};
+    DQMC_GLB T* C = (DQMC_GLB T*)(b ? C1g : C0g);
+    T cp[2][2][4];
+    if (ADD) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool live = (i0 + 16 * r < M) && (j0 + 16 * q < Nc);
+            cp[r][q][v] = live ? C[(size_t)(i0 + 16 * r + out_row<T>(v, lane)) * ldc + j0 + 16 * q + li] : (T)0;
+          }
+    }
     for (int k0 = 0; k0 < K; k0 += 4 * WK_U) {
       T a[WK_U][2], bv[WK_U][2];
 #pragma unroll
@@ -311,9 +326,28 @@ __device__ __forceinline__ void wave_gemm(int nb, int M, int Nc, int K, const T*
       for (int q = 0; q < 2; ++q) {
         if (i0 + 16 * r >= M || j0 + 16 * q >= Nc) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) epi(b, i0 + 16 * r + out_row<T>(v, lane), j0 + 16 * q + li, acc[r][q][v]);
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 16 * r + out_row<T>(v, lane), j = j0 + 16 * q + li;
+          if (ADD) C[(size_t)i * ldc + j] = cp[r][q][v] + acc[r][q][v];
+          else epi(b, i, j, acc[r][q][v]);
+        }
       }
   }
+}
+template <typename T, typename Epi>
+__device__ __forceinline__ void wave_gemm(int nb, int M, int Nc, int K, const T* A0, const T* A1,
+                                          int sai, int sak, const T* B0, const T* B1, int sbk,
+                                          int sbj, Epi epi) {
+  wave_gemm_impl<T, false>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, (T*)nullptr, (T*)nullptr,
+                           0, epi);
+}
+// C_b += A_b B_b (C_b row-major with leading dimension ldc, in global memory).
+template <typename T>
+__device__ __forceinline__ void wave_gemm_add(int nb, int M, int Nc, int K, const T* A0, const T* A1,
+                                              int sai, int sak, const T* B0, const T* B1, int sbk,
+                                              int sbj, T* C0, T* C1, int ldc) {
+  wave_gemm_impl<T, true>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, C0, C1, ldc,
+                          [](int, int, int, T) {});
 }
 
 // ------------------------------------------------------------------------------ reductions
@@ -1836,8 +1870,11 @@ __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldru
       WT* Y0 = c.xy + (size_t)np * K;
       WT* X1 = c.xy + 2 * (size_t)np * K;
       WT* Y1 = c.xy + 3 * (size_t)np * K;
-      ctx_gemm<WT>(c, 2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1,
-                  [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
+      if (c.stage)
+        wave_gemm_add<WT>(2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1, c.G[0], c.G[1], np);
+      else
+        ctx_gemm<WT>(c, 2, np, np, mp, X0, X1, 1, np, Y0, Y1, np, 1,
+                     [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
     }
     __syncthreads();
     clk.stop(c.st, PH_FLUSH);
@@ -1962,8 +1999,7 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
     }
     // ---- G += XA YA when the next block might not fit, and at the end of the slice
     if (mA > 0 && (i0 + K >= n || mA + K > KT)) {
-      ctx_gemm<WT>(c, 2, np, np, mA, XA[0], XA[1], 1, np, YA[0], YA[1], np, 1,
-                   [&](int b, int i, int j, WT v) { c.G[b][i * np + j] += v; });
+      wave_gemm_add<WT>(2, np, np, mA, XA[0], XA[1], 1, np, YA[0], YA[1], np, 1, c.G[0], c.G[1], np);
       __syncthreads();
       clk.stop(c.st, PH_FLUSH);
       mA = 0;
