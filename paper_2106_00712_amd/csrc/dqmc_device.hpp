@@ -537,8 +537,7 @@ template <typename T, typename WT, typename Epi>
 __device__ __forceinline__ void ctx_gemm(Ctx<WT>& c, int nb, int M, int Nc, int K, const T* A0,
                                          const T* A1, int sai, int sak, const T* B0, const T* B1,
                                          int sbk, int sbj, Epi epi) {
-  if (c.stage)
-    gemm_tiled<T>((DQMC_LDS double*)c.stage, nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
+  if (c.stage) wave_gemm<T>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
   else wg_gemm<T>(nb, M, Nc, K, A0, A1, sai, sak, B0, B1, sbk, sbj, epi);
 }
 
