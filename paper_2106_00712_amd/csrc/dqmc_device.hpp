@@ -152,113 +152,22 @@ __device__ __forceinline__ void wg_gemm(int nb, int M, int Nc, int K, const T* A
   }
 }
 
-// ------------------------------------------------------------------------------ tiled products
-// Matrix products for chains whose matrices live in the chain's workspace (N > 64): operands
-// are read from HBM/L2 in coalesced 16-wide K panels, staged through a double-buffered LDS
-// area, and multiplied on the matrix cores in 64 x 64 output macro-tiles (each wavefront a
-// 32 x 32 quadrant of 2 x 2 MFMA tiles).  The operands are read as global memory and the
-// staging area as LDS, so the loads of the next panel stay in flight while the current one is
-// multiplied (vmcnt and lgkmcnt are waited on separately).
-constexpr int TG_M = 64;    // macro-tile rows / columns
-constexpr int TG_K = 16;    // K panel
-// LDS staging in doubles: two buffers of A (K-major, TG_K x TG_M) and B (TG_K x TG_M)
-constexpr int TG_STAGE_DOUBLES = 4 * TG_K * TG_M;
+// ------------------------------------------------------------------------------ workspace products
+// LDS scratch of the workspace kernels' blocked factorisations (partial sums, the current panel's
+// T and pivot block), in doubles; it also sizes their LDS layout on the host.
+constexpr int TG_STAGE_DOUBLES = 4096;
 
-// C_b(i, j) = sum_{k < K} A_b(i, k) B_b(k, j) for b < nb, i < M, j < Nc (M, Nc multiples of 16),
-// A_b(i, k) = A_b[i sai + k sak], B_b(k, j) = B_b[k sbk + j sbj] with unit stride in one of
-// each pair (row- or column-major operands).  The operands must be in global memory (the
-// chain's workspace or the model constants), never in LDS.  epi(b, i, j, value) is called once
-// per output element by the lane that owns it.  All NT threads of the workgroup take part.
-template <typename T, typename Epi>
-__device__ __forceinline__ void gemm_tiled(DQMC_LDS double* stage, int nb, int M, int Nc, int K,
-                                           const T* A0g, const T* A1g, int sai, int sak,
-                                           const T* B0g, const T* B1g, int sbk, int sbj, Epi epi) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches below
-  const int li = lane & 15, lk = lane >> 4;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int mt = (M + TG_M - 1) / TG_M, nt = (Nc + TG_M - 1) / TG_M, kc = (K + TG_K - 1) / TG_K;
-  const DQMC_GLB T* A0 = (const DQMC_GLB T*)A0g;
-  const DQMC_GLB T* A1 = (const DQMC_GLB T*)A1g;
-  const DQMC_GLB T* B0 = (const DQMC_GLB T*)B0g;
-  const DQMC_GLB T* B1 = (const DQMC_GLB T*)B1g;
-  DQMC_LDS T* As[2] = {(DQMC_LDS T*)stage, (DQMC_LDS T*)stage + TG_K * TG_M};
-  DQMC_LDS T* Bs[2] = {(DQMC_LDS T*)stage + 2 * TG_K * TG_M, (DQMC_LDS T*)stage + 3 * TG_K * TG_M};
-  const bool a_rows = (sak == 1);    // A contiguous along k (row-major), else along i
-  const bool b_rows = (sbj == 1);    // B contiguous along j (row-major), else along k
-  // each thread moves 4 consecutive elements of each panel per chunk
-  const int a_i = a_rows ? (tid >> 2) : ((tid & 15) * 4), a_k = a_rows ? ((tid & 3) * 4) : (tid >> 4);
-  const int b_k = b_rows ? (tid >> 4) : ((tid & 3) * 4), b_j = b_rows ? ((tid & 15) * 4) : (tid >> 2);
-  for (int t = 0; t < nb * mt * nt; ++t) {
-    const int b = t / (mt * nt), tt = t - b * (mt * nt);
-    const int m0 = (tt / nt) * TG_M, n0 = (tt - (tt / nt) * nt) * TG_M;
-    const DQMC_GLB T* A = b ? A1 : A0;
-    const DQMC_GLB T* B = b ? B1 : B0;
-    T ra[4], rb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = m0 + a_i + (a_rows ? 0 : u), k = k0 + a_k + (a_rows ? u : 0);
-        ra[u] = (i < M && k < K) ? A[(size_t)i * sai + (size_t)k * sak] : (T)0;
-        const int kk = k0 + b_k + (b_rows ? 0 : u), j = n0 + b_j + (b_rows ? u : 0);
-        rb[u] = (kk < K && j < Nc) ? B[(size_t)kk * sbk + (size_t)j * sbj] : (T)0;
-      }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        As[buf][(a_k + (a_rows ? u : 0)) * TG_M + a_i + (a_rows ? 0 : u)] = ra[u];
-        Bs[buf][(b_k + (b_rows ? 0 : u)) * TG_M + b_j + (b_rows ? u : 0)] = rb[u];
-      }
-    };
-    typename acc4<T>::type acc[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) acc[r][q] = typename acc4<T>::type{0, 0, 0, 0};
-    const bool live_r[2] = {m0 + wr * 32 < M, m0 + wr * 32 + 16 < M};
-    const bool live_c[2] = {n0 + wc * 32 < Nc, n0 + wc * 32 + 16 < Nc};
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int c = 0; c < kc; ++c) {
-      const int cur = c & 1;
-      if (c + 1 < kc) load((c + 1) * TG_K);
-      if (live_r[0] && live_c[0]) {
-#pragma unroll
-        for (int s = 0; s < TG_K / 4; ++s) {
-          const int kr = (4 * s + lk) * TG_M;
-          const T a0 = As[cur][kr + wr * 32 + li], a1 = As[cur][kr + wr * 32 + 16 + li];
-          const T b0 = Bs[cur][kr + wc * 32 + li], b1 = Bs[cur][kr + wc * 32 + 16 + li];
-          acc[0][0] = mfma(a0, b0, acc[0][0]);
-          if (live_c[1]) acc[0][1] = mfma(a0, b1, acc[0][1]);
-          if (live_r[1]) acc[1][0] = mfma(a1, b0, acc[1][0]);
-          if (live_r[1] && live_c[1]) acc[1][1] = mfma(a1, b1, acc[1][1]);
-        }
-      }
-      if (c + 1 < kc) store(cur ^ 1);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (!(live_r[r] && live_c[q])) continue;
-        const int i0 = m0 + wr * 32 + r * 16, j0 = n0 + wc * 32 + q * 16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) epi(b, i0 + out_row<T>(v, lane), j0 + li, acc[r][q][v]);
-      }
-  }
-}
-
-// Thin products of the workspace kernels (one output side <= 32, contraction <= a few hundred):
-// each wavefront computes whole 32 x 32 output tiles on its own, reading its operands straight
-// from global memory with WK_U k-steps of 4 in flight per lane (no LDS staging, no workgroup
-// barrier), where gemm_tiled would give one 64 x 64 tile, half of it idle, to the whole
-// workgroup panel by panel.  The MFMAs see the same inputs in the same k order as in gemm_tiled
-// and wg_gemm (steps of 4 ascending), so the results are the same bits.  Same contract as
-// gemm_tiled: operands in global memory, M and Nc multiples of 16, K a multiple of 4; epi is
-// called once per output element by the lane that owns it.
+// Matrix products of the workspace kernels (N > 64, matrices in the chain's workspace):
+// C_b(i, j) = sum_{k < K} A_b(i, k) B_b(k, j) for b < nb, i < M, j < Nc, with
+// A_b(i, k) = A_b[i sai + k sak] and B_b(k, j) = B_b[k sbk + j sbj].  Each wavefront computes
+// whole 32 x 32 output tiles (2 x 2 MFMA tiles) on its own, reading its operands straight from
+// global memory with WK_U k-steps of 4 in flight per lane: no LDS staging and no workgroup
+// barrier, so the four wavefronts' loads overlap each other's matrix-core work.  (An LDS-staged
+// 64 x 64 macro-tile shared by the workgroup measured slower at these sizes: it waits on memory
+// once per 16-deep panel for the whole workgroup.)  The k order is steps of 4 ascending, as in
+// wg_gemm.  Contract: operands in global memory (the workspace or the model constants), never
+// LDS; M and Nc multiples of 16; K a multiple of 4; epi(b, i, j, value) is called once per
+// output element by the lane that owns it; no barrier inside (callers order the calls).
 // ADD: C_b[i ldc + j] += (A_b B_b)(i, j) instead of epi, with the tile of C loaded together with
 // the first operands (no memory round trip after the products).
 constexpr int WK_U = 8;
@@ -914,7 +823,6 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
                                          DQMC_LDS double* dtmp, double* X, double* A, double* Ud,
                                          double* dd, int* flags) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  DQMC_LDS double* stage = stage_lds;
   double* V = qrv;                         // reflectors, np x np column-major, zero above the diagonal
   double* Tg = qrv + (size_t)np * np;      // T of panel p at Tg[p QB^2], row-major
   DQMC_LDS double* red = stage_lds;        // [NW][QB] partial sums
@@ -1049,7 +957,7 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
       double* W = Ud;
       const double* Vp = V + (size_t)k0 * np + k0;
       const double* C = A + (size_t)(k0 + QB) * np + k0;
-      gemm_tiled<double>(stage, 1, QB, ncr, np - k0, Vp, Vp, np, 1, C, C, 1, np,
+      wave_gemm<double>(1, QB, ncr, np - k0, Vp, Vp, np, 1, C, C, 1, np,
                        [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
       __syncthreads();
       const double* T = Tg + (size_t)pnl * QB * QB;
@@ -1066,7 +974,7 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
         }
       }
       __syncthreads();
-      gemm_tiled<double>(stage, 1, np - k0, ncr, QB, Vp, Vp, 1, np, W, W, np, 1,
+      wave_gemm<double>(1, np - k0, ncr, QB, Vp, Vp, 1, np, W, W, np, 1,
                        [&](int, int i, int j, double v) { A[(size_t)(k0 + QB + j) * np + k0 + i] -= v; });
       __syncthreads();
     }
@@ -1083,7 +991,7 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
     double* W = X;
     const double* Vp = V + (size_t)k0 * np + k0;
     double* Qb = Ud + (size_t)k0 * np + k0;
-    gemm_tiled<double>(stage, 1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
+    wave_gemm<double>(1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
                      [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
     __syncthreads();
     const double* T = Tg + (size_t)pnl * QB * QB;
@@ -1100,7 +1008,7 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
       }
     }
     __syncthreads();
-    gemm_tiled<double>(stage, 1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
+    wave_gemm<double>(1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
                      [&](int, int i, int j, double v) { Qb[(size_t)i * np + j] -= v; });
     __syncthreads();
   }
@@ -1144,7 +1052,6 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
                                             const DQMC_LDS double* bt, const double* X, double* W,
                                             double* Ud) {
   const int tid = threadIdx.x;
-  DQMC_LDS double* stage = stage_lds;
   double* V = qrv;
   double* Tg = qrv + (size_t)np * np;
   for (int e = tid; e < np * np; e += NT) {
@@ -1169,7 +1076,7 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
     const int k0 = pnl * QB, nbk = min(QB, n - k0);
     const double* Vp = V + (size_t)k0 * np + k0;
     double* Tp = Tg + (size_t)pnl * QB * QB;
-    gemm_tiled<double>(stage, 1, QB, QB, np - k0, Vp, Vp, np, 1, Vp, Vp, 1, np,
+    wave_gemm<double>(1, QB, QB, np - k0, Vp, Vp, np, 1, Vp, Vp, 1, np,
                        [&](int, int i, int j, double v) { Tp[i * QB + j] = v; });
     __syncthreads();
     for (int e = tid; e < QB * QB; e += NT) Yl[e] = Tp[e];
@@ -1200,7 +1107,7 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
     const int k0 = pnl * QB, w = np - k0;
     const double* Vp = V + (size_t)k0 * np + k0;
     double* Qb = Ud + (size_t)k0 * np + k0;
-    gemm_tiled<double>(stage, 1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
+    wave_gemm<double>(1, QB, w, w, Vp, Vp, np, 1, Qb, Qb, np, 1,
                        [&](int, int i, int j, double v) { W[(size_t)i * np + j] = v; });
     __syncthreads();
     const double* T = Tg + (size_t)pnl * QB * QB;
@@ -1217,7 +1124,7 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
       }
     }
     __syncthreads();
-    gemm_tiled<double>(stage, 1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
+    wave_gemm<double>(1, w, w, QB, Vp, Vp, 1, np, W, W, np, 1,
                        [&](int, int i, int j, double v) { Qb[(size_t)i * np + j] -= v; });
     __syncthreads();
   }
@@ -1384,7 +1291,6 @@ __device__ __noinline__ double gj_blocked(int n, int np, DQMC_LDS double* stage_
                                           const DQMC_LDS double* rs, double* M, double* Z,
                                           double* dst) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  DQMC_LDS double* stage = stage_lds;
   DQMC_LDS double* red = stage_lds;                     // [NW] argmax keys
   DQMC_LDS int* redi = (DQMC_LDS int*)(red + NW);       // [NW] argmax rows
   DQMC_LDS double* prow = red + 2 * NW;                 // [QB] pivot row, panel part
@@ -1528,7 +1434,7 @@ __device__ __noinline__ double gj_blocked(int n, int np, DQMC_LDS double* stage_
     __syncthreads();
     // rows not in P: x -= M[r, K] W;  rows in P: x = W (their Qp rows are zero)
     if (nmr > 0) {
-      gemm_tiled<double>(stage, 1, np, nmr, QB, Qp, Qp, QB, 1, W, W, ldw, 1,
+      wave_gemm<double>(1, np, nmr, QB, Qp, Qp, QB, 1, W, W, ldw, 1,
                          [&](int, int i, int j, double v) {
                            const int rr = rank[i];
                            double* e = M + (size_t)i * np + k0 + QB + j;
@@ -1536,7 +1442,7 @@ __device__ __noinline__ double gj_blocked(int n, int np, DQMC_LDS double* stage_
                            else *e -= v;
                          });
     }
-    gemm_tiled<double>(stage, 1, np, np, QB, Qp, Qp, QB, 1, W + nmr, W + nmr, ldw, 1,
+    wave_gemm<double>(1, np, np, QB, Qp, Qp, QB, 1, W + nmr, W + nmr, ldw, 1,
                        [&](int, int i, int j, double v) {
                          const int rr = rank[i];
                          double* e = Z + (size_t)i * np + j;
