@@ -827,8 +827,6 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
   double* Tg = qrv + (size_t)np * np;      // T of panel p at Tg[p QB^2], row-major
   DQMC_LDS double* red = stage_lds;        // [NW][QB] partial sums
   DQMC_LDS double* rowv = red + NW * QB;   // [QB] row r0 of the panel
-  DQMC_LDS double* yv = rowv + QB;         // [QB] V(:, i)^T v_j
-  DQMC_LDS double* Tl = yv + QB;           // [QB][QB] T of the current panel
   // 1. pre-pivot: rank of each column by (norm descending, index ascending), a strict order
   for (int col = wave; col < n; col += NW) {
     double s = 0;
@@ -864,7 +862,10 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
   // 3. panels
   for (int k0 = 0, pnl = 0; k0 < n; k0 += QB, ++pnl) {
     const int nbk = min(QB, n - k0);
-    for (int e = tid; e < QB * QB; e += NT) Tl[e] = 0.0;
+    // row tid of the panel's T factor (threads tid < QB): T(i, j) depends on row i only
+    double trow[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) trow[q] = 0.0;
     double p[RPT][QB];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
@@ -919,15 +920,17 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
             if (r >= r0 && r < np) p[m][q] -= w * ((r == r0) ? v0 : p[m][j]);
           }
         }
-        if (tid == 0) {
+        // T(i, j) = -be sum_{k = i}^{j-1} T(i, k) y_k (i < j), T(j, j) = be, y_k = V(:, k)^T v_j
+        if (tid < j) {
+          double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < QB; ++q) yv[q] = z[q] - al * rowv[q];
-          Tl[j * QB + j] = be;
-          for (int i = 0; i < j; ++i) {
-            double acc = 0.0;
-            for (int k = i; k < j; ++k) acc += Tl[i * QB + k] * yv[k];
-            Tl[i * QB + j] = -be * acc;
-          }
+          for (int k = 0; k < j; ++k)
+            if (k >= tid) acc += trow[k] * (z[k] - al * rowv[k]);
+          trow[j] = -be * acc;
+        } else if (tid == j) {
+          trow[j] = be;
+        }
+        if (tid == 0) {
           vdv[r0] = al;
           btv[j] = v0;
         }
@@ -949,7 +952,10 @@ __device__ __noinline__ void udt_blocked(int n, int np, DQMC_LDS double* stage_l
         }
       }
     }
-    for (int e = tid; e < QB * QB; e += NT) Tg[(size_t)pnl * QB * QB + e] = Tl[e];
+    if (tid < QB) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) Tg[(size_t)pnl * QB * QB + tid * QB + q] = trow[q];
+    }
     __syncthreads();
     // trailing columns: C <- C - V (T^T (V^T C)), W = V^T C staged in Ud (free until step 4)
     if (n - k0 - QB > 0) {
@@ -1081,18 +1087,28 @@ __device__ __noinline__ void q_form_blocked(int n, int np, DQMC_LDS double* stag
     __syncthreads();
     for (int e = tid; e < QB * QB; e += NT) Yl[e] = Tp[e];
     __syncthreads();
-    if (tid == 0) {
+    // row i of T on thread i < QB: T(i, j) = -be_j sum_{k = i}^{j-1} T(i, k) Y(k, j) depends on
+    // row i alone
+    if (tid < QB) {
+      double trow[QB];
+#pragma unroll
       for (int j = 0; j < QB; ++j) {
-        for (int i = 0; i < QB; ++i) Tl[i * QB + j] = 0.0;
-        if (j >= nbk) continue;
-        const double be = bt[k0 + j];
-        Tl[j * QB + j] = be;
-        for (int i = 0; i < j; ++i) {
-          double acc = 0.0;
-          for (int k = i; k < j; ++k) acc += Tl[i * QB + k] * Yl[k * QB + j];
-          Tl[i * QB + j] = -be * acc;
+        trow[j] = 0.0;
+        if (j < nbk) {
+          const double be = bt[k0 + j];
+          if (tid == j) {
+            trow[j] = be;
+          } else if (tid < j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < j; ++k)
+              if (k >= tid) acc += trow[k] * Yl[k * QB + j];
+            trow[j] = -be * acc;
+          }
         }
       }
+#pragma unroll
+      for (int j = 0; j < QB; ++j) Tl[tid * QB + j] = trow[j];
     }
     __syncthreads();
     for (int e = tid; e < QB * QB; e += NT) Tp[e] = Tl[e];
