@@ -597,6 +597,9 @@ def main():
                     "N <= 64 kernels (L in 4, 6, 8); warm pools, continuous batching",
             "fp64": [run_serving(rate, 48, fast_L, "fp64", 16, 10, 0) for rate in (100, 1000)],
         }
+        if not args.no_fp32:
+            line["serving"]["fp32_wrap"] = [run_serving(rate, 48, fast_L, "fp32_wrap", 16, 10, 3)
+                                            for rate in (100, 1000)]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_chains, args.cpu_sweeps)
     print(json.dumps(line))
