@@ -105,6 +105,29 @@ def test_graph_replays_equal_eager_sweeps(dq):
     graph.close()
 
 
+def test_own_stream_matches_torch_stream(dq):
+    """dqmc_stream_create / dqmc_stream_destroy: sweeps and a measurement enqueued on a stream of
+    the library's making give the same bits as on torch's current stream; the stream is then
+    destroyed (nothing of torch's refers to it: no pinned buffer was copied on it)."""
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    for n in (16, 100):
+        w2 = di.Workload(f"square{int(n ** 0.5)}", 9, "square", int(n ** 0.5), 4.0, 1.0, 0.1, 3, 1, 5)
+        m = _model(dq, w2)
+        s = dq.stream_create()
+        a = dq.Batch(m, w2.seeds(3), w2.fields(3))
+        b = dq.Batch(m, w2.seeds(3), w2.fields(3))
+        a.sweep(2, stream=s)
+        oa = a.measure(stream=s)
+        fa = a.fields(stream=s)
+        s.synchronize()
+        b.sweep(2)
+        ob = b.measure()
+        _same(oa, fa.cpu().numpy(), ob, b.fields().cpu().numpy())
+        dq.stream_destroy(s)
+        a.close()
+        b.close()
+
+
 def test_padded_small_lattice_uses_fast_path(dq):
     w = di.Workload("square6x6_U4_b2", 7, "square", 6, 4.0, 2.0, 0.1, 2, 2, 10)
     b = dq.Batch(_model(dq, w), w.seeds(2), w.fields(2))
