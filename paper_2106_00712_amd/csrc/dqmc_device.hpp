@@ -1664,10 +1664,16 @@ __device__ __forceinline__ void decide_block(Ctx<WT>& c, int l, int i0, int kb, 
         c.yb[K2 + m * K + r] = (r == ii ? 1.0 : 0.0) - c.gb[K2 + ii * K + r];
       }
       wave_sync();
-      for (int e = lane; e < kb * kb; e += 64) {
-        int r = e / kb, cc = e - r * kb;
-        c.gb[r * K + cc] += c.xb[r * K + m] * c.yb[m * K + cc];
-        c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * c.yb[K2 + m * K + cc];
+      // rank-1 update of the block: lane -> column lane % cw, rows lane / cw + k (64 / cw), with
+      // cw = 16 or 32 >= kb, so no division per element
+      const int cw = (kb <= 16) ? 16 : 32;
+      const int cc = lane & (cw - 1), rstep = 64 / cw;
+      if (cc < kb) {
+        const double yu = c.yb[m * K + cc], yd = c.yb[K2 + m * K + cc];
+        for (int r = lane / cw; r < kb; r += rstep) {
+          c.gb[r * K + cc] += c.xb[r * K + m] * yu;
+          c.gb[K2 + r * K + cc] += c.xb[K2 + r * K + m] * yd;
+        }
       }
       if (lane == 0) {
         c.site[m] = ii;
