@@ -1872,11 +1872,16 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
       // ---- columns and rows of the true G at the accepted sites
       if (mA > 0) {
         const int mr = (mp + 15) & ~15;
-        for (int e = tid; e < 2 * mA * mr; e += NT) {
-          const int b = e / (mA * mr), rem = e - b * (mA * mr), u = rem / mr, t = rem - u * mr;
+        {
+          // thread -> column t = tid % mr (mr = 16 or 32 divides NT), rows u = tid / mr + k NT / mr
+          const int t = tid & (mr - 1), ustep = NT / mr;
           const int col = (t < m) ? i0 + c.site[t] : -1;
-          Ys[b][u * K16 + t] = (col >= 0) ? YA[b][(size_t)u * np + col] : (WT)0;
-          Xs[b][t * KT + u] = (col >= 0) ? XA[b][(size_t)u * np + col] : (WT)0;
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            for (int u = tid / mr; u < mA; u += ustep) {
+              Ys[b][u * K16 + t] = (col >= 0) ? YA[b][(size_t)u * np + col] : (WT)0;
+              Xs[b][t * KT + u] = (col >= 0) ? XA[b][(size_t)u * np + col] : (WT)0;
+            }
         }
         __syncthreads();
         wave_gemm<WT>(2, np, mr, mA, XA[0], XA[1], 1, np, Ys[0], Ys[1], K16, 1,
