@@ -125,7 +125,7 @@ def test_free_fermion_green(lattice, L, beta, stab):
     assert abs(ek - ex.free_kinetic(T, beta)) < 1e-12
 
 
-def test_free_fermion_survey_values():
+def test_free_fermion_kinetic_energies():
     # U = 0 kinetic energies per site, recomputed from the spectrum of T
     for lattice, L, beta, val in (("square", 4, 2.0, -1.463692229945),
                                   ("square", 8, 4.0, -1.566637278560),
