@@ -14,6 +14,7 @@
 #include "dqmc_error.hpp"
 #include "dqmc_device.hpp"
 #include "dqmc_fast.hpp"
+#include "dqmc_kernels.hpp"
 
 using namespace dqmc;
 
@@ -89,52 +90,6 @@ __global__ __launch_bounds__(NT) void constants_kernel(int n, int np, double dta
     }
     __syncthreads();
   }
-}
-
-// ------------------------------------------------------------------------ sweep kernel
-template <typename WT, bool SMALL>
-__global__ __launch_bounds__(NT) void chain_kernel(KArgs a) {
-  extern __shared__ double lds[];
-  const int idx = blockIdx.x;
-  const int chain = a.slots ? a.slots[idx] : idx;
-  if (chain < 0 || chain >= a.n_chains) return;
-  const int n_sweeps = a.counts ? a.counts[chain] : a.n_sweeps;
-  if (a.op == OP_SWEEP && n_sweeps <= 0) return;
-  Ctx<WT> c = make_ctx<WT, SMALL>(a, chain, lds);
-  if (a.op == OP_INIT) {
-    if (threadIdx.x == 0) {
-      ChainStats* st = c.st;
-      st->seed = a.seeds[idx];
-      st->sweeps_done = st->attempted = st->accepted = st->near_ties = 0;
-      st->max_drift = st->max_logdet_err = 0.0;
-      st->logdet[0] = st->logdet[1] = 0.0;
-      st->flags = 0;
-      st->pad = 0;
-      for (int k = 0; k < 16; ++k) st->ticks[k] = 0;
-      st->slice_docc = st->slice_kin = 0.0;
-      st->slice_meas = 0;
-      st->stack_ok = 0;
-      st->pad2 = 0;
-    }
-    __syncthreads();
-    op_init(c, idx);
-  } else if (a.op == OP_SWEEP) {
-    op_sweep(c, n_sweeps);
-  } else if (a.op == OP_DEBUG_GREEN) {
-    op_debug_green(c, chain);
-  } else if (a.op == OP_DEBUG_RATIOS) {
-    op_debug_ratios(c, chain);
-  }
-}
-
-template <int NP, typename WT, int KB>
-__global__ __launch_bounds__(NT) void fast_sweep_kernel(KArgs a) {
-  extern __shared__ double lds[];
-  const int chain = blockIdx.x;
-  if (chain >= a.n_chains) return;
-  const int n_sweeps = a.counts ? a.counts[chain] : a.n_sweeps;
-  if (n_sweeps <= 0) return;
-  fast::Fast<NP, WT, KB>::run(a, chain, n_sweeps, lds);
 }
 
 // ------------------------------------------------------------------------ measurements
@@ -487,28 +442,18 @@ void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KAr
 }
 
 // The kernel a batch runs for an operation, and its LDS bytes.
-struct KernelRef {
-  const void* fn;
-  size_t lds;
-};
-
-template <int NP, typename WT, int KB>
-KernelRef fast_ref() {
-  return {(const void*)fast_sweep_kernel<NP, WT, KB>, fast::Fast<NP, WT, KB>::lds_bytes()};
-}
-
-template <typename WT>
 KernelRef fast_ref(const dqmc_batch* b) {
-  if (b->np == 16) return fast_ref<16, WT, 8>();
-  if (b->np == 32) return b->K == 8 ? fast_ref<32, WT, 8>() : fast_ref<32, WT, 16>();
-  return b->K == 8 ? fast_ref<64, WT, 8>() : fast_ref<64, WT, 16>();
+  const bool f32 = b->precision == DQMC_FP32_WRAP;
+  if (b->np == 16) return f32 ? fast_kernel_f32_np16(b->K) : fast_kernel_f64_np16(b->K);
+  if (b->np == 32) return f32 ? fast_kernel_f32_np32(b->K) : fast_kernel_f64_np32(b->K);
+  return f32 ? fast_kernel_f32_np64(b->K) : fast_kernel_f64_np64(b->K);
 }
 
 KernelRef resolve(const dqmc_batch* b, int op) {
   const bool f32 = b->precision == DQMC_FP32_WRAP;
-  if (op == OP_SWEEP && b->fast) return f32 ? fast_ref<float>(b) : fast_ref<double>(b);
-  const void* fn = f32 ? (b->small ? (const void*)chain_kernel<float, true> : (const void*)chain_kernel<float, false>)
-                       : (b->small ? (const void*)chain_kernel<double, true> : (const void*)chain_kernel<double, false>);
+  if (op == OP_SWEEP && b->fast) return fast_ref(b);
+  const void* fn = f32 ? (b->small ? chain_kernel_f32_lds() : chain_kernel_f32_ws())
+                       : (b->small ? chain_kernel_f64_lds() : chain_kernel_f64_ws());
   return {fn, b->lds_bytes};
 }
 

@@ -1,0 +1,4 @@
+// chain_kernel<float, true>: the LDS-resident Green's function variant in FP32-wrap precision.
+#include "k_chain.hpp"
+
+const void* dqmc::chain_kernel_f32_lds() { return (const void*)chain_kernel<float, true>; }
