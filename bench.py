@@ -114,11 +114,11 @@ def choose_qr(w, mode: str) -> bool:
 
 
 def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh: int,
-            qr_blocked: bool = False, sweep_mode: int = 0):
+            qr_blocked: bool = False, sweep_mode: int = 0, stab: int = 0):
     import torch
     from paper_2106_00712_amd import dqmc
 
-    m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, delay_rank=delay_rank,
+    m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, stab or w.stab_every, delay_rank=delay_rank,
                         precision=precision, refresh_every=refresh, qr_blocked=qr_blocked,
                         sweep_mode=sweep_mode)
     fields = torch.as_tensor(w.fields()).cuda()
@@ -150,14 +150,15 @@ def run_gpu(w, precision: str, steps: int, warmup: int, delay_rank: int, refresh
 
 
 def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick: int,
-                refresh: int, seed: int = 4):
-    """Continuous batching of a Poisson stream of chain requests (lattice L x L, beta, sweep
-    count drawn as in the serving workload), warm pools for every model of the mix."""
+                refresh: int, seed: int = 4, progress: bool = False):
+    """Continuous batching of a Poisson stream of chain requests at `rate` req/s offered (lattice
+    L x L with L uniform over `Ls`, beta and sweep count drawn as in the serving workload), warm
+    pools for every model of the mix."""
     from paper_2106_00712_amd.serving import GpuExecutor, Request, Server, latency_stats
-    reqs = [r for r in di.serving_requests(4 * n_req, rate, seed) if r["L"] in Ls][:n_req]
+    reqs = di.serving_requests(n_req, rate, seed, Ls=tuple(Ls))
     ex = GpuExecutor(di.square_hopping, U=4.0, dtau=0.1, stab_every=10,
                      refresh_every=refresh if precision == "fp32_wrap" else 0)
-    srv = Server(ex, hbm_budget=64 << 30, tick_sweeps=tick, pool_capacity=capacity,
+    srv = Server(ex, hbm_budget=96 << 30, tick_sweeps=tick, pool_capacity=capacity,
                  precision=precision)
     srv.warm([(L, b) for L in Ls for b in di.SERVING_BETA])
     # the arrival times are re-based so that the first request arrives at t = 0
@@ -166,7 +167,8 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
           for d in reqs]
     t0 = time.perf_counter()
     try:
-        res = srv.run(rq)
+        res = srv.run(rq, progress=(lambda msg: print(f"serving {precision} {rate:g} req/s: {msg}",
+                                                      file=sys.stderr, flush=True)) if progress else None)
         wall = time.perf_counter() - t0
     finally:
         srv.close()
@@ -174,14 +176,18 @@ def run_serving(rate: float, n_req: int, Ls, precision: str, capacity: int, tick
     span = rq[-1].arrival if len(rq) > 1 else 0.0
     wait = [r.admitted - r.arrival for r in res]
     service = [r.finished - r.admitted for r in res]
-    return {"rate_req_per_s": rate, "offered_rate_req_per_s": (len(rq) - 1) / span if span > 0 else None,
+    flagged = sum(1 for r in res if int(r.obs["flags"]))
+    return {"rate_req_per_s": rate, "measured_arrival_rate_req_per_s": (len(rq) - 1) / span if span > 0 else None,
             "requests": len(res), "p50_s": st["p50_s"], "p99_s": st["p99_s"],
             "mean_s": st["mean_s"], "wait_p50_s": float(np.median(wait)) if wait else None,
+            "wait_p99_s": float(np.percentile(wait, 99)) if wait else None,
             "service_p50_s": float(np.median(service)) if service else None,
             "hw_queues": GpuExecutor.hw_queues_hint(),
-            "updates_per_s": srv.updates / wall, "wall_s": wall,
+            "updates_per_s": srv.updates / wall, "updates": srv.updates, "wall_s": wall,
             "ticks": srv.ticks, "precision": precision, "lattices_L": list(Ls),
-            "pool_capacity": capacity, "tick_sweeps": tick}
+            "flagged_requests": flagged, "max_drift": float(max(float(r.obs["max_drift"]) for r in res)),
+            "pool_capacity": capacity, "tick_sweeps": tick,
+            "refresh_every": refresh if precision == "fp32_wrap" else None}
 
 
 def run_serving_models(precision: str = "fp64", sweeps_small: int = 10, sweeps_large: int = 2):
@@ -269,41 +275,41 @@ PAPER_TABLE2 = {"E_k": (-1.358, 0.001), "S_Gamma": (3.00, 0.04)}
 def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
     """Thermalised chains at the paper's honeycomb point; E_k and the sublattice-signed S(Gamma)
     per chain (time average over `meas` sweeps, one measurement at G(0) after each sweep), then
-    the mean and standard error over the independent chains."""
+    the mean and standard error over the independent chains.  Every measurement comes from the
+    per-sweep series the sweep kernel records on the device (dqmc_sweep_series), copied to the
+    host once per block of sweeps."""
     import torch
-    from paper_2106_00712_amd import dqmc
+    from paper_2106_00712_amd import analysis, dqmc
     w = di.WORKLOADS["honeycomb6x6_U3.83_b6"]
     eps = di.staggered_sign(w.lattice, w.L)
     m = dqmc.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
     b = dqmc.Batch(m, w.seeds(n_chains, seed_first))
-    from paper_2106_00712_amd import analysis
+    block = 50
+
+    def series(n_sw, label):
+        parts, done = [], 0
+        while done < n_sw:
+            k = min(block, n_sw - done)
+            parts.append(b.sweep_series(k, form=eps).cpu().numpy())
+            done += k
+            print(f"physics: {label} {done}/{n_sw} sweeps", file=sys.stderr, flush=True)
+        return np.concatenate(parts, axis=0) if parts else np.zeros((0, n_chains, 4))
+
     t0 = time.perf_counter()
-    conv_pts = set(range(1, 21)) | set(range(25, therm + 1, 25))
-    conv = {"sweeps": [], "E_k": [], "E_k_se": [], "S_Gamma_moments": [], "S_Gamma_moments_se": []}
-    for k in range(1, therm + 1):
-        b.sweep(1)
-        if k in conv_pts:     # the paper's Fig. 3 form: chain averages after each sweep
-            o = b.measure()
-            sm = 4.0 * b.spin_structure(eps).cpu().numpy()
-            conv["sweeps"].append(k)
-            for key, v in (("E_k", o["kinetic"]), ("S_Gamma_moments", sm)):
-                mu, se = analysis.mean_and_error(v)
-                conv[key].append(mu)
-                conv[key + "_se"].append(se)
-        if k % 50 == 0:
-            print(f"physics: thermalised {k}/{therm} sweeps", file=sys.stderr, flush=True)
+    th = series(therm, "thermalised")          # [therm][chains][4], the Fig. 3 form
     torch.cuda.synchronize()
     t_therm = time.perf_counter() - t0
-    ser = np.zeros((4, n_chains, meas))
-    for k in range(meas):
-        b.sweep(1)
-        o = b.measure()
-        ser[0, :, k] = o["kinetic"]
-        ser[1, :, k] = b.spin_structure(eps).cpu().numpy()
-        ser[2, :, k] = o["double_occ"]
-        ser[3, :, k] = o["density"]
-        if (k + 1) % 50 == 0:
-            print(f"physics: measured {k + 1}/{meas} sweeps", file=sys.stderr, flush=True)
+    conv = {"sweeps": [], "E_k": [], "E_k_se": [], "S_Gamma_moments": [], "S_Gamma_moments_se": []}
+    for k in sorted(set(range(1, 21)) | set(range(25, therm + 1, 25))):
+        if k > therm:
+            continue
+        conv["sweeps"].append(k)
+        for key, v in (("E_k", th[k - 1, :, 2]), ("S_Gamma_moments", 4.0 * th[k - 1, :, 3])):
+            mu, se = analysis.mean_and_error(v)
+            conv[key].append(mu)
+            conv[key + "_se"].append(se)
+    ms = series(meas, "measured")               # [meas][chains][4]
+    ser = np.stack([ms[:, :, 2].T, ms[:, :, 3].T, ms[:, :, 0].T, ms[:, :, 1].T])  # [4][chains][meas]
     o = b.measure()
     wall = time.perf_counter() - t0
     per_chain = ser.mean(axis=2)
@@ -329,6 +335,11 @@ def run_physics(n_chains: int, therm: int, meas: int, seed_first: int = 0):
            "autocorr_S_Gamma": {str(t): float(a_s[t]) for t in (1, 2, 5, 10, 20, 50, 100) if t < len(a_s)},
            "autocorr_E_k": {str(t): float(a_e[t]) for t in (1, 2, 5, 10, 20, 50, 100) if t < len(a_e)},
            "tau_int_S_Gamma": analysis.integrated_time(a_s), "tau_int_E_k": analysis.integrated_time(a_e)}
+    # %OL (20 bins) of the E_k distribution k sweeps after the random starts against the
+    # thermalised one (the paper's overlap measure applied to the Hubbard chains)
+    out["percent_overlap_E_k_vs_thermalised"] = {
+        str(k): analysis.percent_overlap(th[k - 1, :, 2], ser[0].ravel(), 20)
+        for k in (1, 5, 15, 50) if k <= therm}
     for key, (mu, se) in (("E_k", ek), ("S_Gamma_1_over_N", s_n), ("S_Gamma_1_over_L2", s_l2),
                           ("S_Gamma_moments_1_over_N", s_m)):
         pm, pe = PAPER_TABLE2["E_k" if key == "E_k" else "S_Gamma"]
@@ -415,21 +426,80 @@ def fp32_wrap_error(w, n_chains: int, bound: float):
                                         stab_every=w.stab_every)
 
 
-def cpu_baseline(w, n_chains: int, n_sweeps: int):
-    """The CPU oracle, as it is, on a bounded sample of the same workload."""
-    from oracle import Model, OracleChains
+def drift_stats(o, limit: float) -> dict:
+    """Distribution over chains of the drift max|G_wrapped - G_fresh| at the stabilisation
+    (refresh) points of a run, and how many chains crossed `limit` (FLAG_DRIFT)."""
+    d = np.sort(np.asarray(o["max_drift"], dtype=np.float64))
+    return {"max": float(d[-1]), "p50": float(np.median(d)), "p90": float(d[int(0.9 * (len(d) - 1))]),
+            "limit": limit, "flagged_chains": int(np.count_nonzero(np.asarray(o["flags"]) & 4)),
+            "chains": int(len(d))}
 
-    m = Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
-    oc = OracleChains(m, w.fields(n_chains), w.seeds(n_chains))
-    c0, t0 = time.process_time(), time.perf_counter()
-    oc.sweep(n_sweeps)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    upd = n_chains * n_sweeps * w.n_slices * w.n_sites
-    return dict(value=upd / wall, unit="updates/s", cores=max(1, int(round(cpu / wall))),
-                kind="oracle",
-                sample=f"{n_chains} chains x {n_sweeps} sweeps of the {w.name} workload "
-                       f"({upd} updates, {wall:.1f} s wall)")
+
+def tune_delay_rank(w, stab: int, candidates):
+    """The delay rank the autotuner picks for a workload (timed sweeps of the full batch size,
+    at most 256 chains), with its timing table."""
+    from paper_2106_00712_amd.autotune import Autotuner
+    return Autotuner().delay_rank(w.hopping(), w.U, w.dtau, w.n_slices, stab,
+                                  candidates=tuple(candidates), n_chains=min(256, w.n_chains),
+                                  sweeps=3 if w.n_sites <= 64 else 1)
+
+
+def tune_stab(w, bound: float = 1e-6, chains: int = 8):
+    """Stabilisation interval for a workload: the largest candidate whose FP64 drift over two
+    sweeps from the seeded fields stays within `bound` (the autotuner's drift_interval)."""
+    from paper_2106_00712_amd.autotune import Autotuner
+    cands = sorted({c for c in (w.stab_every, 8, 5, 4, 2) if c <= w.stab_every}, reverse=True)
+    return Autotuner().drift_interval(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(chains),
+                                      w.seeds(chains), bound, candidates=cands, precision="fp64")
+
+
+def _cpu_chains(job):
+    """Worker of the CPU baseline: chains [first, first + n) of a workload swept by the oracle in
+    baseline mode with the BLAS on one thread; returns the wall seconds of the sweeps."""
+    name, first, n, n_sweeps = job
+    from threadpoolctl import threadpool_limits
+    from oracle import Model, OracleChains
+    w = di.WORKLOADS[name]
+    with threadpool_limits(1):
+        oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, stacks=True),
+                          w.fields(n, first), w.seeds(n, first))
+        t0 = time.perf_counter()
+        oc.sweep(n_sweeps)
+        return time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, chains_per_proc: int, n_sweeps: int, procs: int = 0):
+    """The CPU oracle, as it is, in baseline mode (right UDT stack per sweep plus a running left
+    factorisation, the GPU's algorithm class) on a bounded sample of the same workload: one
+    process per host core (at most 16, the host share of one GPU), each sweeping its own chains
+    with a single-threaded BLAS.  Run before anything touches the GPU."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    procs = procs or max(1, min(16, ncpu))
+    jobs = [(w.name, p * chains_per_proc, chains_per_proc, n_sweeps) for p in range(procs)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        pool.map(_cpu_chains, jobs[:1])           # start-up (imports) outside the timed region
+        t0 = time.perf_counter()
+        per = pool.map(_cpu_chains, jobs)
+        wall = time.perf_counter() - t0
+    upd = procs * chains_per_proc * n_sweeps * w.n_slices * w.n_sites
+    return dict(value=upd / wall, unit="updates/s", cores=procs, kind="oracle",
+                sample=f"{procs * chains_per_proc} chains x {n_sweeps} sweeps of the {w.name} workload "
+                       f"({upd} updates, {wall:.1f} s wall, {sum(per):.1f} s of sweeps over "
+                       f"{procs} processes), oracle in baseline mode, single-threaded BLAS per process",
+                nproc=ncpu, cpu_model=_cpu_model())
 
 
 def main():
@@ -437,24 +507,32 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--delay-rank", type=int, default=0)
+    ap.add_argument("--delay-rank", default="auto",
+                    help="delay rank k, or 'auto': the autotuner's choice among the workload's candidates")
     ap.add_argument("--refresh", type=int, default=0,
                     help="FP32-wrap FP64 refresh interval (0: the longest within max|dG| <= 1e-5 "
                          "on fixed fields, chosen by the autotuner)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-chains", type=int, default=12)
+    ap.add_argument("--cpu-chains", type=int, default=2, help="CPU baseline: chains per process")
     ap.add_argument("--cpu-sweeps", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-full", action="store_true",
-                    help="only the serving workload over every lattice size (minutes per rate)")
+                    help="only the serving workload over every lattice size (minutes per rate; "
+                         "--precision fp64, fp32_wrap or both)")
+    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 2000.0],
+                    help="with --serving-full: offered request rates (req/s)")
+    ap.add_argument("--requests", type=int, default=1000, help="with --serving-full: requests per rate")
+    ap.add_argument("--capacity", type=int, default=64, help="with --serving-full: slots per model pool")
     ap.add_argument("--serving-models", action="store_true",
                     help="compute time of one request of every serving model (L up to 16), alone")
     ap.add_argument("--workload", default=None,
                     help="only a throughput line for this workload (e.g. square20x20_U8_b10)")
     ap.add_argument("--chains", type=int, default=0, help="with --workload: number of chains")
-    ap.add_argument("--stab", type=int, default=0,
-                    help="with --workload: stabilisation interval in slices (0: the workload's)")
+    ap.add_argument("--stab", default="0",
+                    help="with --workload: stabilisation interval in slices (0: the workload's; "
+                         "'auto': the largest of the workload's interval, 8, 5, 4, 2 whose FP64 "
+                         "drift over two sweeps stays within 1e-6)")
     ap.add_argument("--precision", default="fp64", help="with --workload: fp64 or fp32_wrap")
     ap.add_argument("--mixed", action="store_true",
                     help="only the mixed-size batch: honeycomb 6x6 + 12x12, FP32 wraps, one graph")
@@ -480,11 +558,20 @@ def main():
 
     if args.workload:
         wl = di.WORKLOADS[args.workload]
-        if args.chains or args.stab:
+        stab_tune = tune_stab(wl) if args.stab == "auto" else None
+        stab = stab_tune["interval"] if stab_tune else int(args.stab)
+        if args.chains or stab:
             wl = di.Workload(wl.name, wl.config_id, wl.lattice, wl.L, wl.U, wl.beta, wl.dtau,
-                             args.chains or wl.n_chains, wl.n_sweeps, args.stab or wl.stab_every)
+                             args.chains or wl.n_chains, wl.n_sweeps, stab or wl.stab_every,
+                             delay_ranks=wl.delay_ranks)
         qb = choose_qr(wl, args.qr)
-        r = run_gpu(wl, args.precision, args.steps, args.warmup, args.delay_rank,
+        k_tune = None
+        if args.delay_rank == "auto" and wl.delay_ranks:
+            k_tune = tune_delay_rank(wl, wl.stab_every, wl.delay_ranks)
+            k = k_tune["delay_rank"]
+        else:
+            k = 0 if args.delay_rank == "auto" else int(args.delay_rank)
+        r = run_gpu(wl, args.precision, args.steps, args.warmup, k,
                     (args.refresh or 10) if args.precision == "fp32_wrap" else 0, qr_blocked=qb,
                     sweep_mode=args.sweep_mode)
         o = r["obs"]
@@ -504,6 +591,8 @@ def main():
                           "double_occ": float(o["double_occ"].mean()),
                           "flags": int(np.bitwise_or.reduce(o["flags"])),
                           "flagged_chains": int(np.count_nonzero(o["flags"])),
+                          "drift": drift_stats(o, 1e-5 if args.precision == "fp32_wrap" else 1e-3),
+                          "stab_autotune": stab_tune, "delay_rank_autotune": k_tune,
                           "phase_share": r["phase_share"]}))
         return
     if args.ising:
@@ -523,10 +612,21 @@ def main():
         print(json.dumps({"serving_models": [run_serving_models("fp64"), run_serving_models("fp32_wrap")]}))
         return
     if args.serving_full:
-        out = [run_serving(rate, 48, di.SERVING_L, "fp64", 16, 10, 0) for rate in (50, 2000)]
-        print(json.dumps({"serving_full": out}))
+        # the whole request mix (L up to 16, beta in {2, 4, 8}); one JSON line per rate
+        precs = ["fp64"]
+        if args.precision != "fp64":
+            print("the FP32-wrap serving mix is switched off (an unexplained GPU memory fault in its "
+                  "test); serving FP64 only", file=sys.stderr)
+        for prec in precs:
+            for rate in args.rates:
+                r = run_serving(rate, args.requests, di.SERVING_L, prec, args.capacity, 10,
+                                args.refresh or 3, progress=True)
+                print(json.dumps({"serving_full": r}), flush=True)
         return
 
+    w = di.WORKLOADS[WORKLOAD]
+    # the CPU oracle first, in worker processes started before this process touches the GPU
+    cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_chains, args.cpu_sweeps)
     if args.copy_calibration:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -534,9 +634,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = di.WORKLOADS[WORKLOAD]
     upd_step = w.n_chains * w.n_slices * w.n_sites
-    r64 = run_gpu(w, "fp64", args.steps, args.warmup, args.delay_rank, 0)
+    k_tune = None
+    if args.delay_rank == "auto":
+        k_tune = tune_delay_rank(w, w.stab_every, w.delay_ranks)
+        k = k_tune["delay_rank"]
+    else:
+        k = int(args.delay_rank)
+    r64 = run_gpu(w, "fp64", args.steps, args.warmup, k, 0)
     value = upd_step * args.steps / r64["wall"]
     o = r64["obs"]
     acc = float(o["accepted"].sum() / o["attempted"].sum())
@@ -571,37 +676,60 @@ def main():
         "phase_share": r64["phase_share"],
         "rows": row_rooflines(fl, r64["phase_share"], t_launch, w.n_chains, PEAK_FP64_MFMA),
         "init_ms": r64["init_ms"],
+        "delay_rank_autotune": k_tune,
         "max_drift_fp64": float(o["max_drift"].max()),
         "flags": int(np.bitwise_or.reduce(o["flags"])),
     }
     if not args.no_fp32:
-        werr = fp32_wrap_error(w, 4, 1e-5)
+        from paper_2106_00712_amd.autotune import Autotuner
+        bound = 1e-5
+        werr = fp32_wrap_error(w, 4, bound)          # fixed fields: r* wraps stay within the bound
         refresh = args.refresh or werr["refresh_every"]
-        r32 = run_gpu(w, "fp32_wrap", args.steps, args.warmup, args.delay_rank, refresh)
+        r32 = run_gpu(w, "fp32_wrap", args.steps, args.warmup, k, refresh)
         o32 = r32["obs"]
         v32 = upd_step * args.steps / r32["wall"]
+        # in sweeps: the drift at the refresh points of a short run for every interval down to 1
+        sw = Autotuner().drift_interval(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(64),
+                                        w.seeds(64), bound, candidates=(5, 4, 3, 2, 1),
+                                        precision="fp32_wrap", sweeps=2, stab_every=w.stab_every)
+        # cost of one stabilisation point, from FP64 at half the interval: t = t_core + J t_stab
+        r64h = run_gpu(w, "fp64", 10, 2, k, 0, stab=w.stab_every // 2)
+        J = lambda st: -(-w.n_slices // st)
+        t64 = t_launch
+        t64h = float(np.mean(r64h["per_launch_ms"])) * 1e-3
+        t32 = float(np.mean(r32["per_launch_ms"])) * 1e-3
+        t_stab = (t64h - t64) / (J(w.stab_every // 2) - J(w.stab_every))
+        core64 = t64 - J(w.stab_every) * t_stab
+        core32 = t32 - J(refresh) * t_stab
         line["fp32_wrap"] = {"value": v32, "unit": "updates/s", "refresh_every": refresh,
                              "ms_per_step": r32["wall"] * 1e3 / args.steps,
+                             "speedup_vs_fp64": v32 / value,
+                             "bound": bound,
                              "max_abs_dG_fixed_fields": werr["max_abs_dG"].get(str(refresh)),
                              "fixed_field_wrap_error": werr,
-                             "max_abs_dG_at_refresh_in_sweeps": float(o32["max_drift"].max()),
-                             "speedup_vs_fp64": v32 / value,
+                             "in_sweep_drift": drift_stats(o32, bound),
+                             "fp64_in_sweep_drift": drift_stats(o, 1e-3),
+                             "in_sweep_drift_by_refresh": sw,
+                             "cost_model_ms": {"stabilisation_point": t_stab * 1e3,
+                                               "fp64_core": core64 * 1e3, "fp32_core": core32 * 1e3,
+                                               "fp32_at_fp64_interval": (core32 + J(w.stab_every) * t_stab) * 1e3,
+                                               "fp64": t64 * 1e3, "fp64_half_interval": t64h * 1e3,
+                                               "fp32": t32 * 1e3},
                              "phase_share": r32["phase_share"],
                              "double_occ": float(o32["double_occ"].mean()),
-                             "double_occ_fp64": float(o["double_occ"].mean()),
-                             "flags": int(np.bitwise_or.reduce(o32["flags"]))}
+                             "double_occ_fp64": float(o["double_occ"].mean())}
     if not args.no_serving:
         fast_L = tuple(L for L in di.SERVING_L if L * L <= 64)
         line["serving"] = {
-            "note": "Poisson stream of the serving workload restricted to the lattices of the "
-                    "N <= 64 kernels (L in 4, 6, 8); warm pools, continuous batching",
+            "note": "Poisson stream of the serving workload drawn over the lattices of the "
+                    "N <= 64 kernels (L in 4, 6, 8) at the offered rate; warm pools, continuous "
+                    "batching (the whole mix, L up to 16, is bench.py --serving-full)",
             "fp64": [run_serving(rate, 48, fast_L, "fp64", 16, 10, 0) for rate in (100, 1000)],
         }
-        if not args.no_fp32:
-            line["serving"]["fp32_wrap"] = [run_serving(rate, 48, fast_L, "fp32_wrap", 16, 10, 3)
-                                            for rate in (100, 1000)]
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_chains, args.cpu_sweeps)
+        # the FP32-wrap serving mix made an unexplained GPU memory fault in a test; it stays off
+        line["serving"]["fp32_wrap"] = None
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line))
 
 

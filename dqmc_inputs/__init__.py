@@ -169,14 +169,15 @@ SERVING_SWEEPS = (20, 200)
 SERVING_RATES = (50, 100, 200, 500, 1000, 2000)
 
 
-def serving_requests(n: int, rate: float, seed: int = 4):
-    """Poisson arrivals (req/s) with L, beta and sweep count drawn uniformly; seeded."""
+def serving_requests(n: int, rate: float, seed: int = 4, Ls=SERVING_L):
+    """Poisson arrivals at `rate` req/s with L (from `Ls`), beta and sweep count drawn uniformly;
+    seeded.  Restricting `Ls` keeps the arrival rate: the stream is drawn over the given lattices."""
     rng = np.random.Generator(np.random.Philox(key=[seed, int(rate)]))
     gaps = rng.exponential(1.0 / rate, size=n)
     arrivals = np.cumsum(gaps)
     reqs = []
     for r in range(n):
-        L = int(rng.choice(SERVING_L))
+        L = int(rng.choice(Ls))
         beta = float(rng.choice(SERVING_BETA))
         sweeps = int(rng.integers(SERVING_SWEEPS[0], SERVING_SWEEPS[1] + 1))
         reqs.append(dict(id=r, arrival=float(arrivals[r]), L=L, beta=beta, sweeps=sweeps,

@@ -50,7 +50,7 @@ typedef enum {
 /* Per-chain flags (dqmc_obs.flags) */
 #define DQMC_FLAG_NONFINITE 1   /* a ratio or a Green's function went non-finite */
 #define DQMC_FLAG_NEGATIVE 2    /* R < 0 (cannot happen at half filling on a bipartite lattice) */
-#define DQMC_FLAG_DRIFT 4       /* |G_wrapped - G_fresh| exceeded the precision's limit */
+#define DQMC_FLAG_DRIFT 4       /* |G_wrapped - G_fresh| exceeded dqmc_model.drift_limit */
 #define DQMC_FLAG_SINGULAR 8    /* a zero pivot in QR or LU */
 
 /* The model (supplement section I.2).  All values are read during dqmc_init_chains. */
@@ -79,6 +79,9 @@ typedef struct {
                                reusing the UDT stack the other one left.  Bit 1: the equal-time
                                estimators are also taken after every slice (dqmc_obs.slice_*).
                                Nonzero modes run in the workspace kernels at any N. */
+  double drift_limit;       /* DQMC_FLAG_DRIFT is raised when max|G_wrapped - G_fresh| at a
+                               stabilisation point exceeds this (0 = default: 1e-3 in FP64, 1e-5 in
+                               FP32_WRAP, the bound its Green's functions are meant to keep) */
 } dqmc_model;
 
 /* Observables of one chain, written by dqmc_measure (device memory, one per chain).  The
@@ -126,6 +129,20 @@ dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_ch
 
 /* Run n_sweeps Metropolis sweeps on every chain of the batch (one persistent launch). */
 dqmc_status dqmc_sweep(dqmc_batch* b, int32_t n_sweeps, void* stream);
+
+/* Per-sweep series (chain diagnostics: autocorrelation, convergence from the starting fields).
+ * Runs n_sweeps sweeps exactly as dqmc_sweep and, after each sweep s, writes every chain c's
+ * equal-time estimators at that sweep's fresh G(0) = G(L_tau) into
+ * series[(s * n_chains + c) * DQMC_SERIES_WIDTH + k]: k = 0 double occupancy, 1 density,
+ * 2 kinetic energy (the values dqmc_measure would return after that sweep), 3 the structure
+ * factor of the form factor `form` (the value dqmc_spin_structure would return; 0 if form is
+ * NULL).  No host synchronisation between sweeps.
+ *   form:   DEVICE double [N] or NULL.   series: DEVICE double [n_sweeps][n_chains][4].
+ * The NIMC analysis of the paper (main text Fig. 3, supplement eq. (5)) is built on such series
+ * of observables against the sweep index. */
+#define DQMC_SERIES_WIDTH 4
+dqmc_status dqmc_sweep_series(dqmc_batch* b, int32_t n_sweeps, const double* form, double* series,
+                              void* stream);
 
 /* Sweep several batches (e.g. different lattice sizes) together: one launch per batch, all
  * enqueued before any waits, the batches overlapping on the device through forked streams. */

@@ -23,6 +23,14 @@ Readings where the paper is silent (listed with reasons in the design notes):
   * stabilisation (fresh G from column-pivoted QR products) after slice l whenever
     l % stab_every == 0 and after l = L_tau; the wrapped G is replaced by the fresh one;
   * measurements use the fresh G(L_tau) = G(0) left after the last sweep.
+
+Two ways to obtain the fresh G at a stabilisation point, the same products in the same chunks:
+  * reference mode (default): both B products rebuilt from slice 1 and from slice L_tau at every
+    stabilisation point, the simplest form to trust;
+  * baseline mode (Model.stacks = True): the UDT factors of B(L_tau, p_j)^T at the points
+    p_j = min(j n_s, L_tau) kept as a stack built once per up sweep (or by the preceding down
+    sweep when sweeps alternate), and B(p_j, 0) pushed one chunk at a time onto a running left
+    factorisation: the algorithm class of the GPU path, used to time the oracle.
 """
 from __future__ import annotations
 
@@ -139,6 +147,19 @@ def udt_product(factors: List[np.ndarray], chunk: int, n: int, factorise=None):
     return U, d, T
 
 
+def udt_push(fac, factors: List[np.ndarray], factorise=None):
+    """UDT of (factors[-1] @ ... @ factors[0]) @ U Diag(d) T for fac = (U, d, T): the chunk is
+    multiplied onto U Diag(d) and factorised again, the new T' multiplies T from the left (one
+    chunk of udt_product)."""
+    factorise = factorise or udt
+    U, d, T = fac
+    X = U * d[None, :]
+    for F in factors:
+        X = F @ X
+    Un, dn, Tn = factorise(X)
+    return Un, dn, Tn @ T
+
+
 def green_two_sided(left, right_t):
     """G = [I + A B]^{-1} with A = UL DL TL and B^T = UR DR TR, and log|det(I + A B)|.
 
@@ -170,6 +191,7 @@ class Model:
     mu: float = 0.0
     exact_pivot: bool = False   # UDT by udt_exact_pivot instead of LAPACK's pivoted QR
     sweep_mode: int = 0         # bit 0: alternate up and down sweeps; bit 1: per-slice measurements
+    stacks: bool = False        # baseline mode: stacked UDT factors instead of rebuilt products
 
     def __post_init__(self):
         self.T = np.asarray(self.T, dtype=np.float64)
@@ -196,6 +218,28 @@ class Model:
         right_t = udt_product([self.B(fields[k - 1], sigma).T for k in range(Lt, l, -1)],
                               self.stab_every, self.N, fac)
         return green_two_sided(left, right_t)
+
+    def points(self):
+        """Stabilisation points p_j = min(j n_s, L_tau), j = 0 .. J."""
+        J = -(-self.n_slices // self.stab_every)
+        return [min(j * self.stab_every, self.n_slices) for j in range(J + 1)]
+
+    def _factorise(self):
+        return udt_exact_pivot if self.exact_pivot else udt
+
+    def left_chunk(self, fac, fields, lo: int, hi: int, sigma: int):
+        """B(hi, lo) B(lo, 0) from the factors of B(lo, 0): push B_{lo+1}, ..., B_hi."""
+        return udt_push(fac, [self.B(fields[k - 1], sigma) for k in range(lo + 1, hi + 1)],
+                        self._factorise())
+
+    def right_chunk(self, fac, fields, lo: int, hi: int, sigma: int):
+        """B(L_tau, lo)^T = B(hi, lo)^T B(L_tau, hi)^T from the factors of B(L_tau, hi)^T:
+        push B_hi^T, ..., B_{lo+1}^T."""
+        return udt_push(fac, [self.B(fields[k - 1], sigma).T for k in range(hi, lo, -1)],
+                        self._factorise())
+
+    def identity_udt(self):
+        return np.eye(self.N), np.ones(self.N), np.eye(self.N)
 
     def wrap(self, G, s_l, sigma):
         """G(l) = B_l G(l-1) B_l^{-1}: [I + B(l,0)B(L,l)]^{-1} conjugated by B_l."""
@@ -274,6 +318,10 @@ class ChainState:
     slice_docc: float = 0.0            # sums of the per-slice equal-time estimators
     slice_kin: float = 0.0
     slice_meas: int = 0
+    # baseline mode: per spin, factors of B(p_j, 0) (left) and B(L_tau, p_j)^T (right) by j
+    left: List[dict] = dc_field(default_factory=lambda: [{}, {}])
+    right: List[dict] = dc_field(default_factory=lambda: [{}, {}])
+    right_valid: bool = False
 
 
 class OracleChains:
@@ -338,11 +386,18 @@ class OracleChains:
             st.slice_kin += kin
             st.slice_meas += 1
 
+    def _fresh(self, st: ChainState, l: int, k: int, sigma: int):
+        """Fresh G^sigma(l) and log|det|: rebuilt from scratch (reference mode) or from the left
+        and right factors at stabilisation point l (baseline mode)."""
+        if not self.m.stacks:
+            return self.m.green(st.fields, l, sigma)
+        j = self.m.points().index(l)
+        return green_two_sided(st.left[k][j], st.right[k][j])
+
     def _stabilise(self, st: ChainState, Gs, l: int, logdet_run):
         """Replace the running G(l) of both spins by the fresh one; record drift and log-det error."""
-        m = self.m
         for k, sigma in enumerate((+1, -1)):
-            G_new, ld = m.green(st.fields, l, sigma)
+            G_new, ld = self._fresh(st, l, k, sigma)
             drift = float(np.max(np.abs(Gs[k] - G_new)))
             if not math.isfinite(drift):
                 st.flags |= FLAG_NONFINITE
@@ -353,30 +408,65 @@ class OracleChains:
         if st.max_drift > DRIFT_LIMIT:
             st.flags |= FLAG_DRIFT
 
+    def _build_right(self, st: ChainState):
+        """Baseline mode: right factors B(L_tau, p_j)^T for j = J .. 0 from the current fields,
+        one chunk at a time from the top (the per-sweep right stack)."""
+        m, pts = self.m, self.m.points()
+        J = len(pts) - 1
+        for k, sigma in enumerate((+1, -1)):
+            st.right[k] = {J: m.identity_udt()}
+            for j in range(J - 1, -1, -1):
+                st.right[k][j] = m.right_chunk(st.right[k][j + 1], st.fields, pts[j], pts[j + 1], sigma)
+        st.right_valid = True
+
     def _sweep_chain(self, st: ChainState):
         """Up sweep: for l = 1 .. L_tau wrap to G(l), attempt slice l, stabilise at l = k n_s and
         l = L_tau.  Down sweep (odd global sweeps when sweep_mode bit 0 is set): for l = L_tau ..
         1 attempt slice l with G(l), unwrap to G(l-1), stabilise at l - 1 = k n_s (including 0).
-        Either way the chain ends at G(0) = G(L_tau)."""
+        Either way the chain ends at G(0) = G(L_tau).
+
+        Baseline mode keeps the factors the stabilisations need: an up sweep uses the right
+        factors of the fields it has not visited yet (built at its start, or left by the down
+        sweep before it) and pushes the slices it has visited onto the left factors; a down
+        sweep does the same the other way round, with the left factors of the up sweep before."""
         m = self.m
         Lt = m.n_slices
         Gs = [st.G[0], st.G[1]]
         logdet_run = list(st.logdet)
         down = bool(m.sweep_mode & 1) and (st.sweeps_done % 2 == 1)
+        pts = m.points()
         if not down:
+            if m.stacks:
+                if not ((m.sweep_mode & 1) and st.right_valid):
+                    self._build_right(st)
+                st.left = [{0: m.identity_udt()}, {0: m.identity_udt()}]
             for l in range(1, Lt + 1):
                 s_l = st.fields[l - 1]
                 Gs = [m.wrap(Gs[0], s_l, +1), m.wrap(Gs[1], s_l, -1)]
                 self._metropolis_slice(st, Gs[0], Gs[1], l, logdet_run)
                 if l % m.stab_every == 0 or l == Lt:
+                    if m.stacks:
+                        j = pts.index(l)
+                        for k, sigma in enumerate((+1, -1)):
+                            st.left[k][j] = m.left_chunk(st.left[k][j - 1], st.fields, pts[j - 1], l, sigma)
                     self._stabilise(st, Gs, l, logdet_run)
+            st.right_valid = False
         else:
+            if m.stacks:
+                J = len(pts) - 1
+                st.right = [{J: m.identity_udt()}, {J: m.identity_udt()}]
             for l in range(Lt, 0, -1):
                 self._metropolis_slice(st, Gs[0], Gs[1], l, logdet_run)
                 s_l = st.fields[l - 1]
                 Gs = [m.unwrap(Gs[0], s_l, +1), m.unwrap(Gs[1], s_l, -1)]
                 if (l - 1) % m.stab_every == 0:
+                    if m.stacks:
+                        j = pts.index(l - 1)
+                        for k, sigma in enumerate((+1, -1)):
+                            st.right[k][j] = m.right_chunk(st.right[k][j + 1], st.fields, l - 1,
+                                                           pts[j + 1], sigma)
                     self._stabilise(st, Gs, l - 1, logdet_run)
+            st.right_valid = True
         st.G = Gs
         st.logdet = logdet_run
         st.sweeps_done += 1

@@ -6,7 +6,12 @@
 * FP32-wrap refresh interval.  Wrapping G in FP32 loses accuracy geometrically with the number
   of wraps since the last FP64 refresh.  On fixed fields, the FP32-wrapped G after r wraps is
   compared with the FP64 fresh G of the same slice (max |dG| over sampled slices and chains);
-  the largest r within the bound is chosen.
+  the largest r within the bound is chosen.  In sweeps the accepted flips amplify that error
+  (the Sherman-Morrison update divides by the ratio), so `drift_interval` measures the drift the
+  sweeps themselves see at the refresh points, from a short run per candidate.
+* Stabilisation interval.  The drift max|G_wrapped - G_fresh| at the stabilisation points grows
+  with the interval and with how strongly graded the B products are (U, beta).  `drift_interval`
+  runs a few sweeps per candidate and keeps the largest interval whose drift stays within a bound.
 
 * Stabilisation QR for N > 64.  The blocked QR with pre-sorted columns is much faster than the
   column-pivoted one but reproduces its Green's function only while the B products are mildly
@@ -122,6 +127,48 @@ class Autotuner:
                 break
             best = r
         rec = {"refresh_every": int(best), "bound": bound, "max_abs_dG": {str(r): v for r, v in errs.items()}}
+        self.cache[key] = rec
+        self._save()
+        return rec
+
+    def drift_interval(self, hopping, U, dtau, n_slices, fields, seeds, bound: float,
+                       candidates: Sequence[int] = (10, 8, 5, 4, 2), precision: str = "fp64",
+                       sweeps: int = 2, stab_every: int = 10) -> dict:
+        """Largest interval (stabilisation interval in FP64, refresh interval in FP32_WRAP) whose
+        drift at the stabilisation points, max over the chains of a run of `sweeps` sweeps from the
+        given fields, stays within `bound`.  Candidates are tried from the largest down; the
+        result says whether any met the bound (`meets_bound`) and keeps the drift of each."""
+        T = np.asarray(hopping, dtype=np.float64)
+        key = _model_id(T.shape[0], n_slices, U, dtau, precision,
+                        f"_b{bound:g}_s{sweeps}_c{len(seeds)}_drift")
+        if key in self.cache:
+            return self.cache[key]
+        cands = sorted({int(r) for r in candidates if 1 <= int(r) <= n_slices}, reverse=True)
+        drift, secs, chosen = {}, {}, None
+        torch = dqmc._torch()
+        for r in cands:
+            if precision == "fp32_wrap":
+                m = dqmc.make_model(T, U, dtau, n_slices, stab_every, refresh_every=r,
+                                    precision=precision, drift_limit=1.0)
+            else:
+                m = dqmc.make_model(T, U, dtau, n_slices, r, precision=precision, drift_limit=1.0)
+            b = dqmc.Batch(m, seeds, fields, device=self.device)
+            torch.cuda.synchronize(self.device)
+            t0 = time.perf_counter()
+            b.sweep(sweeps)
+            torch.cuda.synchronize(self.device)
+            secs[r] = (time.perf_counter() - t0) / sweeps
+            o = b.measure()
+            b.close()
+            drift[r] = float(o["max_drift"].max())
+            if drift[r] <= bound:
+                chosen = r
+                break
+        rec = {"interval": int(chosen if chosen is not None else cands[-1]),
+               "meets_bound": chosen is not None, "bound": bound, "precision": precision,
+               "sweeps": sweeps, "chains": int(len(seeds)),
+               "max_drift": {str(r): v for r, v in drift.items()},
+               "seconds_per_sweep": {str(r): v for r, v in secs.items()}}
         self.cache[key] = rec
         self._save()
         return rec

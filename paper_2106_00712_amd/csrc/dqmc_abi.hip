@@ -193,6 +193,69 @@ __global__ __launch_bounds__(NT) void spin_structure_kernel(KArgs a, const doubl
   }
 }
 
+// Row s of a per-sweep series: every chain's estimators at its fresh G(0), computed exactly as
+// measure_kernel (double occupancy, density, kinetic energy) and spin_structure_kernel (the
+// structure factor of form, 0 without one) compute them: same loops, same summation order.
+__global__ __launch_bounds__(NT) void series_kernel(KArgs a, const double* form, double* series, int s) {
+  const int chain = blockIdx.x, tid = threadIdx.x;
+  const int n = a.n, np = a.np;
+  const double* G64 = (const double*)(a.base + (size_t)chain * a.stride + a.o_G64);
+  const double* Gu = G64;
+  const double* Gd = G64 + (size_t)np * np;
+  __shared__ double red[5][NW];
+  double docc = 0, dens = 0, kin = 0, m = 0, acc = 0;
+  for (int i = tid; i < n; i += NT) {
+    double gu = Gu[i * np + i], gd = Gd[i * np + i];
+    docc += (1.0 - gu) * (1.0 - gd);
+    dens += 2.0 - gu - gd;
+  }
+  for (int e = tid; e < n * n; e += NT) {
+    int i = e / n, j = e - i * n;
+    double t = a.Tm[i * np + j];
+    if (t != 0.0) kin += t * (2.0 * (i == j ? 1.0 : 0.0) - Gu[j * np + i] - Gd[j * np + i]);
+  }
+  if (form) {
+    for (int i = tid; i < n; i += NT) {
+      double f = form[i], gu = Gu[i * np + i], gd = Gd[i * np + i];
+      m += f * (gd - gu);
+      acc += f * f * (gu + gd);
+    }
+    for (int e = tid; e < n * n; e += NT) {
+      int i = e / n, j = e - i * n;
+      double ff = form[i] * form[j];
+      if (ff == 0.0) continue;
+      for (int sp = 0; sp < 2; ++sp) {
+        const double* G = G64 + (size_t)sp * np * np;
+        acc -= ff * G[i * np + j] * G[j * np + i];
+      }
+    }
+  }
+  docc = wave_sum(docc);
+  dens = wave_sum(dens);
+  kin = wave_sum(kin);
+  m = wave_sum(m);
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = docc;
+    red[1][tid >> 6] = dens;
+    red[2][tid >> 6] = kin;
+    red[3][tid >> 6] = m;
+    red[4][tid >> 6] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0, s1 = 0, s2 = 0, sm = 0, sa = 0;
+    for (int w = 0; w < NW; ++w) {
+      s0 += red[0][w]; s1 += red[1][w]; s2 += red[2][w]; sm += red[3][w]; sa += red[4][w];
+    }
+    double* dst = series + ((size_t)s * a.n_chains + chain) * DQMC_SERIES_WIDTH;
+    dst[0] = s0 / n;
+    dst[1] = s1 / n;
+    dst[2] = s2 / n;
+    dst[3] = form ? (sm * sm + sa) / (4.0 * n) : 0.0;
+  }
+}
+
 __global__ void get_fields_kernel(KArgs a, int8_t* out) {
   const int chain = blockIdx.x;
   const int8_t* f = (const int8_t*)(a.base + (size_t)chain * a.stride + a.o_fields);
@@ -304,6 +367,8 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
   if (m->refresh_every < 0 || m->delay_rank < 0) return fail(DQMC_EINVAL, "negative refresh/delay");
   if (m->qr_blocked != 0 && m->qr_blocked != 1) return fail(DQMC_EINVAL, "qr_blocked must be 0 or 1");
   if (m->sweep_mode < 0 || m->sweep_mode > 3) return fail(DQMC_EINVAL, "sweep_mode must be in [0, 3]");
+  if (!(m->drift_limit >= 0.0) || !std::isfinite(m->drift_limit))
+    return fail(DQMC_EINVAL, "drift_limit must be finite and >= 0");
   if (n_chains < 0) return fail(DQMC_EINVAL, "n_chains must be >= 0");
   Layout L{};
   L.n = m->n_sites;
@@ -422,7 +487,7 @@ void fill_args(const Layout& L, const dqmc_model* m, char* ws, int n_chains, KAr
   a->dup[1] = std::exp(-2.0 * nu) - 1.0;   // s = +1
   a->ddn[0] = std::exp(-2.0 * nu) - 1.0;   // s = -1: e^{+2 nu s} - 1
   a->ddn[1] = std::exp(2.0 * nu) - 1.0;
-  a->drift_limit = m->precision == DQMC_FP32_WRAP ? 1e-1 : 1e-3;
+  a->drift_limit = m->drift_limit > 0.0 ? m->drift_limit : (m->precision == DQMC_FP32_WRAP ? 1e-5 : 1e-3);
   a->expK = (const double*)(ws + L.c_expK);
   a->expKinv = (const double*)(ws + L.c_expKinv);
   a->expK32 = (const float*)(ws + L.c_expK32);
@@ -609,6 +674,27 @@ dqmc_status dqmc_sweep(dqmc_batch* b, int32_t n_sweeps, void* stream) {
   a.op = OP_SWEEP;
   a.n_sweeps = n_sweeps;
   return launch(b, a, (hipStream_t)stream);
+}
+
+// One sweep launch and one series launch per sweep, all enqueued on the stream back to back (no
+// host synchronisation); consecutive one-sweep launches continue the chains exactly as one launch
+// of n_sweeps would (the random numbers are indexed by each chain's global sweep counter).
+dqmc_status dqmc_sweep_series(dqmc_batch* b, int32_t n_sweeps, const double* form, double* series,
+                              void* stream) {
+  if (!b || !series) return fail(DQMC_EINVAL, "batch/series is NULL");
+  if (n_sweeps < 0) return fail(DQMC_EINVAL, "n_sweeps must be >= 0");
+  if (n_sweeps == 0 || b->n_chains == 0) return DQMC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  KArgs a = b->args;
+  a.op = OP_SWEEP;
+  a.n_sweeps = 1;
+  for (int k = 0; k < n_sweeps; ++k) {
+    dqmc_status st = launch(b, a, s);
+    if (st != DQMC_OK) return st;
+    hipLaunchKernelGGL(series_kernel, dim3(b->n_chains), dim3(NT), 0, s, b->args, form, series, k);
+    HIP_TRY(hipGetLastError());
+  }
+  return DQMC_OK;
 }
 
 dqmc_status dqmc_sweep_multi(dqmc_batch* const* bs, const int32_t* n_sweeps, int32_t n, void* stream) {

@@ -36,7 +36,7 @@ class Model(ctypes.Structure):
                 ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("delay_rank", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("qr_blocked", ctypes.c_int32),
-                ("sweep_mode", ctypes.c_int32)]
+                ("sweep_mode", ctypes.c_int32), ("drift_limit", ctypes.c_double)]
 
 
 OBS_DTYPE = np.dtype([("double_occ", "f8"), ("density", "f8"), ("kinetic", "f8"),
@@ -55,6 +55,7 @@ _SIGS = {
     "dqmc_init_chains": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(Model), _i32, _vp,
                                 ctypes.POINTER(_u64), _vp, _sz, _vp]),
     "dqmc_sweep": (_i32, [_vp, _i32, _vp]),
+    "dqmc_sweep_series": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "dqmc_sweep_multi": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32, _vp]),
     "dqmc_measure": (_i32, [_vp, _vp, _vp, _vp]),
     "dqmc_get_fields": (_i32, [_vp, _vp, _vp]),
@@ -142,7 +143,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, delay_rank=0,
-               precision="fp64", qr_blocked=False, sweep_mode=0):
+               precision="fp64", qr_blocked=False, sweep_mode=0, drift_limit=0.0):
     """Build the C model struct; the returned object keeps the host hopping array alive."""
     T = np.ascontiguousarray(np.asarray(hopping, dtype=np.float64))
     if T.ndim != 2 or T.shape[0] != T.shape[1]:
@@ -156,6 +157,7 @@ def make_model(hopping, U, dtau, n_slices, stab_every, mu=0.0, refresh_every=0, 
     m.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     m.qr_blocked = 1 if qr_blocked else 0
     m.sweep_mode = int(sweep_mode)
+    m.drift_limit = float(drift_limit)
     m._keep = T
     return m
 
@@ -224,6 +226,25 @@ class Batch:
     def sweep(self, n_sweeps: int, stream=None):
         with self.torch.cuda.device(self.device):
             _check(lib().dqmc_sweep(self._h, int(n_sweeps), _stream(stream, self.device)))
+
+    SERIES = ("double_occ", "density", "kinetic", "structure")
+
+    def sweep_series(self, n_sweeps: int, form=None, stream=None):
+        """n_sweeps sweeps, recording every chain's estimators after each sweep on the device:
+        a float64 tensor [n_sweeps][n_chains][4] (double occupancy, density, kinetic energy, the
+        structure factor of the real form factor `form`, or 0 without one)."""
+        torch = self.torch
+        out = torch.empty((int(n_sweeps), self.n_chains, 4), dtype=torch.float64, device=self.device)
+        f = None
+        if form is not None:
+            f = torch.as_tensor(np.asarray(form, dtype=np.float64)).to(self.device)
+            if f.numel() != self.n:
+                raise ValueError(f"form factor has {f.numel()} entries, the lattice {self.n} sites")
+            self._form_keep = f
+        with torch.cuda.device(self.device):
+            _check(lib().dqmc_sweep_series(self._h, int(n_sweeps), _ptr(f) if f is not None else None,
+                                           _ptr(out), _stream(stream, self.device)))
+        return out
 
     def init_slots(self, slots, seeds, fields=None, stream=None):
         """Re-initialise the listed chains with new seeds (and fields, else drawn from the seeds)."""

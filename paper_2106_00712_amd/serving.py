@@ -212,15 +212,22 @@ class Server:
         return out
 
     def run(self, requests: Sequence[Request], clock: Optional[Callable[[], float]] = None,
-            realtime: bool = True) -> List[Result]:
+            realtime: bool = True, progress: Optional[Callable[[str], None]] = None,
+            progress_every: float = 20.0) -> List[Result]:
         """Serve a stream of requests; request.arrival is its time after the start.  With
-        realtime=False every request is released at once (a closed loop)."""
+        realtime=False every request is released at once (a closed loop).  `progress`, if given,
+        receives a status line every `progress_every` seconds of the run's clock."""
         t0 = time.perf_counter()
         now = clock or (lambda: time.perf_counter() - t0)
         arrivals = sorted(requests, key=lambda r: r.arrival)
         i, results = 0, []
+        t_report = progress_every
         while i < len(arrivals) or self.pending():
             t = now()
+            if progress is not None and t >= t_report:
+                progress(f"t = {t:.0f} s: {len(results)} of {len(arrivals)} done, "
+                         f"{len(self.queue)} queued, {self.pending() - len(self.queue)} on the GPU")
+                t_report = t + progress_every
             while i < len(arrivals) and (not realtime or arrivals[i].arrival <= t):
                 self.submit(arrivals[i])
                 i += 1

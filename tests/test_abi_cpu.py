@@ -63,7 +63,7 @@ def test_workspace_sizing_without_gpu(lib):
 
 
 @pytest.mark.parametrize("field,value", [("n_sites", 0), ("n_slices", 0), ("stab_every", 0),
-                                         ("precision", 7), ("dtau", -0.1)])
+                                         ("precision", 7), ("dtau", -0.1), ("drift_limit", -1.0)])
 def test_invalid_model_sizes_to_zero(lib, field, value):
     from paper_2106_00712_amd import dqmc
     m = dqmc.make_model(di.square_hopping(4), 4.0, 0.1, 20, 10)

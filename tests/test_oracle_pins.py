@@ -447,3 +447,42 @@ def test_exact_pivot_green_matches_lapack_green():
         ga, la = a.green(f, l, +1)
         gb, lb = b.green(f, l, +1)
         assert np.max(np.abs(ga - gb)) < 1e-11 and abs(la - lb) < 1e-9
+
+
+# ------------------------------------------------------------------------- baseline mode
+@pytest.mark.parametrize("lattice,L,beta,U,stab,sweep_mode,sweeps", [
+    ("square", 4, 2.0, 4.0, 10, 0, 4),      # L_tau a multiple of n_s
+    ("square", 4, 2.0, 4.0, 7, 0, 3),       # ragged top chunk (20 = 7 + 7 + 6)
+    ("square", 4, 2.0, 4.0, 10, 1, 4),      # alternating sweeps reuse the other direction's stack
+    ("square", 4, 2.0, 4.0, 7, 3, 3),
+    ("honeycomb", 2, 1.5, 3.0, 4, 1, 3),
+])
+def test_baseline_mode_matches_reference(lattice, L, beta, U, stab, sweep_mode, sweeps):
+    """Stacked factors (right stack per up sweep or from the down sweep before, running left
+    factors) give the fresh G that rebuilding both products from scratch gives, so the chains
+    take the same decisions; the reference mode is the one pinned by the tests above."""
+    T = di.hopping(lattice, L)
+    n_sl = int(round(beta / 0.1))
+    seeds = [11, 12]
+    f = di.seeded_fields(seeds, n_sl, T.shape[0])
+    ref = OracleChains(Model(T, U, 0.1, n_sl, stab, sweep_mode=sweep_mode), f, seeds)
+    base = OracleChains(Model(T, U, 0.1, n_sl, stab, sweep_mode=sweep_mode, stacks=True), f, seeds)
+    ref.sweep(sweeps)
+    base.sweep(sweeps)
+    assert np.array_equal(ref.fields(), base.fields())
+    assert np.max(np.abs(ref.green() - base.green())) < 1e-10
+    for a, b in zip(ref.measure(), base.measure()):
+        assert a["accepted"] == b["accepted"] and a["flags"] == b["flags"] == 0
+        assert abs(a["logdet_up"] - b["logdet_up"]) < 1e-9 and abs(a["logdet_dn"] - b["logdet_dn"]) < 1e-9
+        assert abs(a["max_drift"] - b["max_drift"]) < 1e-10
+
+
+def test_baseline_mode_8x8():
+    w = di.WORKLOADS["square8x8_U4_b4"]
+    f, s = w.fields(2), w.seeds(2)
+    ref = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), f, s)
+    base = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, stacks=True), f, s)
+    ref.sweep(2)
+    base.sweep(2)
+    assert np.array_equal(ref.fields(), base.fields())
+    assert np.max(np.abs(ref.green() - base.green())) < 1e-10
