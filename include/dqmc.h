@@ -208,6 +208,26 @@ const char* dqmc_last_error(void);
 dqmc_status dqmc_stream_create(void** out);
 dqmc_status dqmc_stream_destroy(void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call hipMalloc: under HIP
+ * graph capture, in tight serving loops, in harnesses that forbid it): the sequence
+ * dqmc_init_chains -> dqmc_sweep(n_sweeps) -> dqmc_measure (and dqmc_get_fields) in one call, on
+ * the same kernels and with the same results, the chains' state held in a static device array of
+ * the library (DQMC_STATIC_BYTES on each GPU it runs on, kept until the process ends) instead of
+ * a caller workspace, and no host handle.  It allocates no device or host memory.
+ *   m, n_chains, fields, seeds: as dqmc_init_chains.   n_sweeps >= 0.
+ *   obs:        DEVICE dqmc_obs [n_chains], required.
+ *   green:      DEVICE double [n_chains][2][N][N] or NULL (both spins' G(0) after the sweeps).
+ *   fields_out: DEVICE int8 [n_chains][n_slices][N] or NULL (the fields after the sweeps).
+ * Returns EINVAL when dqmc_workspace_bytes(m, n_chains) exceeds DQMC_STATIC_BYTES (and for the
+ * reasons dqmc_init_chains gives), ENUMERIC as dqmc_measure (outputs written regardless).  Waits
+ * for its work.  All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (each call initialises what it uses): calls that overlap on one GPU, from several
+ * host threads or on streams not ordered with each other, race and must be serialised. */
+#define DQMC_STATIC_BYTES ((size_t)64 << 20)
+dqmc_status dqmc_run_static(const dqmc_model* m, int32_t n_chains, const int8_t* fields,
+                            const uint64_t* seeds, int32_t n_sweeps, dqmc_obs* obs, double* green,
+                            int8_t* fields_out, void* stream);
+
 /* Numbers the library chose: site-block size k, stabilisation interval, LDS bytes of the sweep
  * kernel, and the sweep kernel variant (0 = generic with LDS-resident Green's functions,
  * 1 = generic with Green's functions in the workspace, 2 = the N <= 64 register/LDS path). */

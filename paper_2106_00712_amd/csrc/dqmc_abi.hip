@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,18 +21,22 @@ using namespace dqmc;
 
 namespace {
 
-thread_local std::string g_err;
+// The last error message of the calling thread, in a fixed buffer (setting it allocates nothing).
+thread_local char g_err[512];
 
-dqmc_status fail(dqmc_status s, const std::string& msg) {
-  g_err = msg;
+dqmc_status fail(dqmc_status s, const char* msg) {
+  std::snprintf(g_err, sizeof g_err, "%s", msg);
   return s;
 }
+dqmc_status fail(dqmc_status s, const std::string& msg) { return fail(s, msg.c_str()); }
 
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(DQMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    if (e_ != hipSuccess) {                                                              \
+      std::snprintf(g_err, sizeof g_err, "%s: %s", #expr, hipGetErrorString(e_));        \
+      return DQMC_EDEVICE;                                                               \
+    }                                                                                    \
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -44,7 +49,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int TAYLOR_DEGREE = 18;
 
 __global__ __launch_bounds__(NT) void constants_kernel(int n, int np, double dtau, double mu, int s,
-                                                      const double* Tp, double* A, double* E0,
+                                                      double* Tp, double* A, double* E0,
                                                       double* E1, double* expK, double* expKinv,
                                                       float* expK32, float* expKinv32, double* eye,
                                                       double* ones, int* err) {
@@ -55,6 +60,11 @@ __global__ __launch_bounds__(NT) void constants_kernel(int n, int np, double dta
     eye[e] = (i == j && i < n) ? 1.0 : 0.0;
   }
   for (int i = tid; i < np; i += NT) ones[i] = 1.0;
+  // the hopping matrix arrives as its n x n block of the np x np array: zero the padding
+  for (int e = tid; e < np * np; e += NT) {
+    int i = e / np, j = e - i * np;
+    if (!(i < n && j < n)) Tp[e] = 0.0;
+  }
   const double scale = std::ldexp(dtau, -s);
   for (int pass = 0; pass < 2; ++pass) {
     const double sg = pass == 0 ? -1.0 : 1.0;   // e^{-dtau(T-mu)} then e^{+dtau(T-mu)}
@@ -254,6 +264,18 @@ __global__ __launch_bounds__(NT) void series_kernel(KArgs a, const double* form,
     dst[2] = s2 / n;
     dst[3] = form ? (sm * sm + sa) / (4.0 * n) : 0.0;
   }
+}
+
+// OR of every chain's flags (obs[0 .. n_chains)) into *out; one block.
+__global__ __launch_bounds__(NT) void flags_or_kernel(const dqmc_obs* obs, int n_chains, int* out) {
+  __shared__ int acc;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  int f = 0;
+  for (int c = threadIdx.x; c < n_chains; c += NT) f |= obs[c].flags;
+  if (f) atomicOr(&acc, f);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = acc;
 }
 
 __global__ void get_fields_kernel(KArgs a, int8_t* out) {
@@ -573,13 +595,103 @@ SidePool& side_pool() {
 
 }  // namespace
 
+namespace {
+
+// Everything dqmc_init_chains does once the layout is known and the workspace is checked: the
+// model constants, the chains' fields, seeds and initial Green's functions.  Fills *b (the
+// caller's storage) and waits for its work; allocates nothing.
+dqmc_status init_core(dqmc_batch* b, const Layout& L, const dqmc_model* m, int32_t n_chains,
+                      const int8_t* fields, const uint64_t* seeds, char* ws, size_t ws_bytes,
+                      hipStream_t s) {
+  if (!m->hopping) return fail(DQMC_EINVAL, "hopping is NULL");
+  if (n_chains > 0 && !seeds) return fail(DQMC_EINVAL, "seeds is NULL");
+  double norm1 = 0.0;
+  for (int j = 0; j < L.n; ++j) {
+    double col = 0.0;
+    for (int i = 0; i < L.n; ++i) {
+      const double t = m->hopping[i * L.n + j];
+      if (!std::isfinite(t) || t != m->hopping[j * L.n + i])
+        return fail(DQMC_EINVAL, "hopping must be finite and symmetric");
+      col += std::fabs(m->dtau * (t - (i == j ? m->mu : 0.0)));
+    }
+    norm1 = std::max(norm1, col);
+  }
+  int sq = 0;
+  while (std::ldexp(norm1, -sq) > 0.5) ++sq;
+  // the n x n hopping block into the np x np array (the constants kernel zeroes the padding)
+  HIP_TRY(hipMemcpy2DAsync(ws + L.c_T, (size_t)L.np * 8, m->hopping, (size_t)L.n * 8, (size_t)L.n * 8,
+                           (size_t)L.n, hipMemcpyHostToDevice, s));
+  if (n_chains > 0)
+    HIP_TRY(hipMemcpyAsync(ws + L.c_seeds, seeds, (size_t)n_chains * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(constants_kernel, dim3(1), dim3(NT), 0, s, L.n, L.np, m->dtau, m->mu, sq,
+                     (double*)(ws + L.c_T), (double*)(ws + L.c_A), (double*)(ws + L.c_E0),
+                     (double*)(ws + L.c_E1), (double*)(ws + L.c_expK), (double*)(ws + L.c_expKinv),
+                     (float*)(ws + L.c_expK32), (float*)(ws + L.c_expKinv32),
+                     (double*)(ws + L.c_eye), (double*)(ws + L.c_ones), (int*)(ws + L.c_err));
+  HIP_TRY(hipGetLastError());
+  b->n = L.n; b->np = L.np; b->L = L.L; b->stab = L.stab; b->J = L.J; b->K = L.K;
+  b->n_chains = n_chains; b->precision = L.precision; b->small = L.small; b->lds_bytes = L.lds_bytes;
+  b->fast = L.fast; b->fast_lds_bytes = L.fast_lds_bytes;
+  b->ws = ws; b->ws_bytes = ws_bytes;
+  b->c_seeds = L.c_seeds; b->c_slots = L.c_slots; b->c_err = L.c_err;
+  fill_args(L, m, ws, n_chains, &b->args);
+  KArgs a = b->args;
+  a.op = OP_INIT;
+  a.gen_fields = fields ? 0 : 1;
+  a.fields_in = fields;
+  a.seeds = (const uint64_t*)(ws + L.c_seeds);
+  dqmc_status st = launch(b, a, s);
+  if (st != DQMC_OK) return st;
+  int err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, ws + L.c_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) return fail(DQMC_EINVAL, "fields must be +1 or -1");
+  return DQMC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ static workspace
+// The chains' state of dqmc_run_static: a file-scope device array, one copy per GPU, held until
+// the process ends.  In host code its name is not a device address: the address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that address
+// (rounded up to 256 bytes, the workspace alignment; the array has 256 bytes of slack for it) is
+// passed to kernels and copies.  The runtime finds a device variable by its name among the code
+// object's exported symbols, so the array has external linkage (an internal-linkage array is a
+// local symbol there, which hipGetSymbolAddress cannot resolve); "used": no device code names it.
+__device__ __attribute__((used, aligned(256))) char dqmc_static_scratch[DQMC_STATIC_BYTES + 256];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::atomic<char*> g_scratch[MAX_DEVICES];
+
+// Device address of the current device's copy of dqmc_static_scratch.
+dqmc_status scratch_ptr(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DQMC_EDEVICE, "device index out of range");
+  char* p = g_scratch[dev].load();
+  if (!p) {
+    void* q = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&q, HIP_SYMBOL(dqmc_static_scratch)));
+    if (!q) return fail(DQMC_EDEVICE, "hipGetSymbolAddress(dqmc_static_scratch) gave NULL");
+    p = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    g_scratch[dev].store(p);
+  }
+  *out = p;
+  return DQMC_OK;
+}
+
+}  // namespace
+
 // Error message shared with the other translation units of the library (dqmc_last_error).
 dqmc_status dqmc::set_error(dqmc_status s, const std::string& msg) { return fail(s, msg); }
 
 // ------------------------------------------------------------------------ C ABI
 extern "C" {
 
-const char* dqmc_last_error(void) { return g_err.c_str(); }
+const char* dqmc_last_error(void) { return g_err; }
 
 size_t dqmc_chain_bytes(const dqmc_model* m) {
   Layout L;
@@ -601,66 +713,15 @@ dqmc_status dqmc_init_chains(dqmc_batch** out, const dqmc_model* m, int32_t n_ch
   Layout L;
   dqmc_status st = make_layout(m, n_chains, &L, true);
   if (st != DQMC_OK) return st;
-  if (!m->hopping) return fail(DQMC_EINVAL, "hopping is NULL");
-  if (n_chains > 0 && !seeds) return fail(DQMC_EINVAL, "seeds is NULL");
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(DQMC_EINVAL, "workspace must be 256-byte aligned");
   const size_t need = L.c_end + (size_t)n_chains * L.stride;
   if (ws_bytes < need) return fail(DQMC_ENOMEM, "workspace too small: need " + std::to_string(need));
-  for (int i = 0; i < L.n; ++i)
-    for (int j = 0; j < L.n; ++j) {
-      double t = m->hopping[i * L.n + j];
-      if (!std::isfinite(t) || t != m->hopping[j * L.n + i])
-        return fail(DQMC_EINVAL, "hopping must be finite and symmetric");
-    }
-  hipStream_t s = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  // padded hopping matrix and seeds to the device
-  std::vector<double> Tp((size_t)L.np * L.np, 0.0);
-  double norm1 = 0.0;
-  for (int j = 0; j < L.n; ++j) {
-    double col = 0.0;
-    for (int i = 0; i < L.n; ++i) {
-      Tp[(size_t)i * L.np + j] = m->hopping[i * L.n + j];
-      col += std::fabs(m->dtau * (m->hopping[i * L.n + j] - (i == j ? m->mu : 0.0)));
-    }
-    norm1 = std::max(norm1, col);
-  }
-  int sq = 0;
-  while (std::ldexp(norm1, -sq) > 0.5) ++sq;
-  HIP_TRY(hipMemcpyAsync(ws + L.c_T, Tp.data(), Tp.size() * 8, hipMemcpyHostToDevice, s));
-  if (n_chains > 0)
-    HIP_TRY(hipMemcpyAsync(ws + L.c_seeds, seeds, (size_t)n_chains * 8, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(constants_kernel, dim3(1), dim3(NT), 0, s, L.n, L.np, m->dtau, m->mu, sq,
-                     (const double*)(ws + L.c_T), (double*)(ws + L.c_A), (double*)(ws + L.c_E0),
-                     (double*)(ws + L.c_E1), (double*)(ws + L.c_expK), (double*)(ws + L.c_expKinv),
-                     (float*)(ws + L.c_expK32), (float*)(ws + L.c_expKinv32),
-                     (double*)(ws + L.c_eye), (double*)(ws + L.c_ones), (int*)(ws + L.c_err));
-  HIP_TRY(hipGetLastError());
   dqmc_batch* b = new (std::nothrow) dqmc_batch;
   if (!b) return fail(DQMC_EDEVICE, "host allocation failed");
-  b->n = L.n; b->np = L.np; b->L = L.L; b->stab = L.stab; b->J = L.J; b->K = L.K;
-  b->n_chains = n_chains; b->precision = L.precision; b->small = L.small; b->lds_bytes = L.lds_bytes;
-  b->fast = L.fast; b->fast_lds_bytes = L.fast_lds_bytes;
-  b->ws = ws; b->ws_bytes = ws_bytes;
-  b->c_seeds = L.c_seeds; b->c_slots = L.c_slots; b->c_err = L.c_err;
-  fill_args(L, m, ws, n_chains, &b->args);
-  KArgs a = b->args;
-  a.op = OP_INIT;
-  a.gen_fields = fields ? 0 : 1;
-  a.fields_in = fields;
-  a.seeds = (const uint64_t*)(ws + L.c_seeds);
-  st = launch(b, a, s);
-  if (st != DQMC_OK) { delete b; return st; }
-  int err = 0;
-  hipError_t e1 = hipMemcpyAsync(&err, ws + L.c_err, sizeof(int), hipMemcpyDeviceToHost, s);
-  hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s) : e1;
-  if (e2 != hipSuccess) {
+  st = init_core(b, L, m, n_chains, fields, seeds, (char*)workspace, ws_bytes, (hipStream_t)stream);
+  if (st != DQMC_OK) {
     delete b;
-    return fail(DQMC_EDEVICE, std::string("init: ") + hipGetErrorString(e2));
-  }
-  if (err) {
-    delete b;
-    return fail(DQMC_EINVAL, "fields must be +1 or -1");
+    return st;
   }
   *out = b;
   return DQMC_OK;
@@ -913,6 +974,53 @@ dqmc_status dqmc_graph_launch(dqmc_graph* g, void* stream) {
 
 dqmc_status dqmc_graph_destroy(dqmc_graph* g) {
   delete g;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_run_static(const dqmc_model* m, int32_t n_chains, const int8_t* fields,
+                            const uint64_t* seeds, int32_t n_sweeps, dqmc_obs* obs, double* green,
+                            int8_t* fields_out, void* stream) {
+  if (!obs) return fail(DQMC_EINVAL, "obs is NULL");
+  if (n_sweeps < 0) return fail(DQMC_EINVAL, "n_sweeps must be >= 0");
+  Layout L;
+  dqmc_status st = make_layout(m, n_chains, &L, true);
+  if (st != DQMC_OK) return st;
+  const size_t need = L.c_end + (size_t)n_chains * L.stride;
+  if (need > DQMC_STATIC_BYTES) {
+    std::snprintf(g_err, sizeof g_err,
+                  "dqmc_run_static: %zu bytes of chain state exceed the static array (%zu bytes)",
+                  need, (size_t)DQMC_STATIC_BYTES);
+    return DQMC_EINVAL;
+  }
+  char* ws = nullptr;
+  st = scratch_ptr(&ws);
+  if (st != DQMC_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  dqmc_batch b;
+  st = init_core(&b, L, m, n_chains, fields, seeds, ws, DQMC_STATIC_BYTES, s);
+  if (st != DQMC_OK) return st;
+  if (n_chains == 0) return DQMC_OK;
+  if (n_sweeps > 0) {
+    KArgs a = b.args;
+    a.op = OP_SWEEP;
+    a.n_sweeps = n_sweeps;
+    st = launch(&b, a, s);
+    if (st != DQMC_OK) return st;
+  }
+  hipLaunchKernelGGL(measure_kernel, dim3(n_chains), dim3(NT), 0, s, b.args, obs, green);
+  HIP_TRY(hipGetLastError());
+  if (fields_out) {
+    hipLaunchKernelGGL(get_fields_kernel, dim3(n_chains), dim3(256), 0, s, b.args, fields_out);
+    HIP_TRY(hipGetLastError());
+  }
+  // every chain's flags into the workspace's second error word, then to the host
+  int* fw = (int*)(ws + L.c_err) + 1;
+  hipLaunchKernelGGL(flags_or_kernel, dim3(1), dim3(NT), 0, s, (const dqmc_obs*)obs, n_chains, fw);
+  HIP_TRY(hipGetLastError());
+  int flags = 0;
+  HIP_TRY(hipMemcpyAsync(&flags, fw, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (flags) return fail(DQMC_ENUMERIC, "a chain raised a numerical flag");
   return DQMC_OK;
 }
 

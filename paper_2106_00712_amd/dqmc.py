@@ -71,6 +71,8 @@ _SIGS = {
     "dqmc_graph_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32]),
     "dqmc_graph_launch": (_i32, [_vp, _vp]),
     "dqmc_graph_destroy": (_i32, [_vp]),
+    "dqmc_run_static": (_i32, [ctypes.POINTER(Model), _i32, _vp, ctypes.POINTER(_u64), _i32, _vp,
+                               _vp, _vp, _vp]),
     "dqmc_debug_green": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "dqmc_debug_ratios": (_i32, [_vp, _i32, _vp, _vp]),
     "dqmc_debug_propagators": (_i32, [_vp, _vp, _vp]),
@@ -356,6 +358,43 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+STATIC_BYTES = 64 << 20
+
+
+def run_static(model: Model, seeds, fields=None, n_sweeps: int = 1, green: bool = False,
+               get_fields: bool = True, device="cuda:0", stream=None):
+    """dqmc_run_static: init, n_sweeps sweeps and the measurement in one call, in the library's
+    static device array (no workspace).  Returns (obs, green or None, fields or None); the output
+    buffers are allocated here, by the caller of the entry point."""
+    torch = _torch()
+    dev = torch.device(device)
+    seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    n = int(seeds.shape[0])
+    N, L = model.n_sites, model.n_slices
+    keep = None
+    fptr = ctypes.c_void_p(0)
+    if fields is not None:
+        f = fields if isinstance(fields, torch.Tensor) else torch.as_tensor(
+            np.ascontiguousarray(np.asarray(fields, dtype=np.int8)))
+        keep = f.to(device=dev, dtype=torch.int8).contiguous()
+        if tuple(keep.shape) != (n, L, N):
+            raise ValueError(f"fields must be [{n}][{L}][{N}]")
+        fptr = _ptr(keep)
+    obs = torch.empty(max(1, n) * OBS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    g = torch.empty((n, 2, N, N), dtype=torch.float64, device=dev) if green else None
+    fo = torch.empty((n, L, N), dtype=torch.int8, device=dev) if get_fields else None
+    with torch.cuda.device(dev):
+        st = lib().dqmc_run_static(ctypes.byref(model), n, fptr,
+                                   seeds.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), int(n_sweeps),
+                                   _ptr(obs), _ptr(g) if g is not None else None,
+                                   _ptr(fo) if fo is not None else None, _stream(stream, dev))
+    if st not in (0, -4):
+        _check(st)
+    del keep
+    o = np.frombuffer(obs.cpu().numpy().tobytes(), dtype=OBS_DTYPE)[:n]
+    return o, g, fo
 
 
 def sweep_multi(batches, n_sweeps, stream=None):
