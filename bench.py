@@ -38,8 +38,10 @@ import dqmc_inputs as di  # noqa: E402
 PEAK_FP64_MFMA = 78.6e12     # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32_MFMA = 157.3e12    # MI355X dense FP32 matrix, FLOP/s
 WORKLOAD = "square8x8_U4_b4"
+# the sources that define the headline kernel (fast_sweep_kernel<64, double, 16>)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_00712_amd", "csrc", f)
-                  for f in ("dqmc_device.hpp", "dqmc_fast.hpp", "dqmc_stab.hpp", "dqmc_abi.hip")]
+                  for f in ("dqmc_device.hpp", "dqmc_fast.hpp", "dqmc_stab.hpp", "philox.hpp",
+                            "k_fast.hpp", "k_fast_f64_np64.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast_sweep_kernel_square8x8.json")
 
 

@@ -64,12 +64,13 @@ class Autotuner:
             return self.cache[key]
         torch = dqmc._torch()
         seeds = np.arange(n_chains, dtype=np.uint64) + np.uint64(seed)
-        timings, seen = {}, {}
+        timings, seen, eff_of = {}, {}, {}
         for k in candidates:
             m = dqmc.make_model(T, U, dtau, n_slices, stab_every, refresh_every=refresh_every,
                                 delay_rank=k, precision=precision)
             b = dqmc.Batch(m, seeds, device=self.device)
             eff = b.delay_rank
+            eff_of[k] = int(eff)
             if eff in seen:
                 timings[k] = seen[eff]
                 b.close()
@@ -84,7 +85,9 @@ class Autotuner:
             timings[k] = dt
             b.close()
         best = min(timings, key=lambda k: timings[k])
-        rec = {"delay_rank": int(best), "seconds_per_sweep": {str(k): v for k, v in timings.items()}}
+        rec = {"delay_rank": int(best), "effective_delay_rank": eff_of[best],
+               "seconds_per_sweep": {str(k): v for k, v in timings.items()},
+               "effective": {str(k): v for k, v in eff_of.items()}}
         self.cache[key] = rec
         self._save()
         return rec
