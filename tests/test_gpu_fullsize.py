@@ -118,4 +118,6 @@ def test_fixed_field_green_full_batch(dq, name, slice_, n_chains, sample, qr_blo
             spread = max(spread, float(np.max(np.abs(alt - ref))) / scale)
         err = float(np.max(np.abs(g[c] - ref))) / scale
         tol = max(1e-10, 4.0 * spread)
+        print(f"{name} chain {c}: max|dG|/max(1,|G|) {err:.2e}, bar {tol:.2e} "
+              f"(spread of correct FP64 evaluations {spread:.2e})")
         assert err < tol, (name, c, err, tol)
