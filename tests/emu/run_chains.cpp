@@ -1,0 +1,74 @@
+// Test-only: the library's C ABI on the host emulation (emu_hip.h).  Reads a model, fields and
+// seeds from DIR (header.txt, hop.bin, fields.bin, seeds.bin), runs dqmc_init_chains, n_sweeps
+// one-sweep dqmc_sweep calls, dqmc_measure and dqmc_get_fields, and writes obs.bin, green.bin and
+// fields_out.bin to DIR.  The workspace is one exact-size heap block, so AddressSanitizer sees
+// any access past it; EMU_WS_FILL and EMU_LDS_FILL set the bytes the workspace and LDS start with.
+// usage: run_chains DIR
+#include "emu_hip.h"
+#include "dqmc.h"
+#include "dqmc_device.hpp"
+
+void emu_call_kernel(const void* fn, void** params) {
+  auto k = reinterpret_cast<void (*)(dqmc::KArgs)>(const_cast<void*>(fn));
+  k(*reinterpret_cast<dqmc::KArgs*>(params[0]));
+}
+
+template <typename T>
+static std::vector<T> readf(const std::string& p, size_t n) {
+  std::vector<T> v(n);
+  FILE* f = std::fopen(p.c_str(), "rb");
+  if (!f || std::fread(v.data(), sizeof(T), n, f) != n) { std::fprintf(stderr, "read %s\n", p.c_str()); std::exit(2); }
+  std::fclose(f);
+  return v;
+}
+template <typename T>
+static void writef(const std::string& p, const T* d, size_t n) {
+  FILE* f = std::fopen(p.c_str(), "wb");
+  std::fwrite(d, sizeof(T), n, f);
+  std::fclose(f);
+}
+
+int main(int argc, char** argv) {
+  std::string dir = argv[1];
+  FILE* h = std::fopen((dir + "/header.txt").c_str(), "r");
+  int n, L, stab, prec, refresh, k, n_chains, n_sweeps, have_fields;
+  double drift, U, dtau;
+  if (std::fscanf(h, "%d %d %d %d %d %d %lf %lf %lf %d %d %d", &n, &L, &stab, &prec, &refresh, &k, &drift, &U,
+                  &dtau, &n_chains, &n_sweeps, &have_fields) != 12) return 2;
+  std::fclose(h);
+  auto hop = readf<double>(dir + "/hop.bin", (size_t)n * n);
+  auto seeds = readf<uint64_t>(dir + "/seeds.bin", n_chains);
+  std::vector<int8_t> fields;
+  if (have_fields) fields = readf<int8_t>(dir + "/fields.bin", (size_t)n_chains * L * n);
+  dqmc_model m{};
+  m.n_sites = n; m.hopping = hop.data(); m.U = U; m.mu = 0.0; m.dtau = dtau; m.n_slices = L;
+  m.stab_every = stab; m.refresh_every = refresh; m.delay_rank = k;
+  m.precision = prec ? DQMC_FP32_WRAP : DQMC_FP64; m.drift_limit = drift;
+  const size_t ws = dqmc_workspace_bytes(&m, n_chains);
+  char* w = (char*)std::aligned_alloc(256, (ws + 255) & ~(size_t)255);
+  const char* wf = std::getenv("EMU_WS_FILL");
+  std::memset(w, wf ? (int)std::strtol(wf, nullptr, 0) : 0xA5, ws);
+  dqmc_batch* b = nullptr;
+  int st = dqmc_init_chains(&b, &m, n_chains, have_fields ? fields.data() : nullptr, seeds.data(), w, ws, nullptr);
+  std::fprintf(stderr, "init: %d %s\n", st, st ? dqmc_last_error() : "");
+  if (st) return 1;
+  int kk, ss, lds, var;
+  dqmc_batch_info(b, &kk, &ss, &lds, &var);
+  std::fprintf(stderr, "k %d stab %d lds %d variant %d\n", kk, ss, lds, var);
+  for (int s = 0; s < n_sweeps; ++s) {
+    st = dqmc_sweep(b, 1, nullptr);
+    std::fprintf(stderr, "sweep %d: %d\n", s, st);
+  }
+  std::vector<dqmc_obs> obs(n_chains);
+  std::vector<double> green((size_t)n_chains * 2 * n * n);
+  st = dqmc_measure(b, obs.data(), green.data(), nullptr);
+  std::fprintf(stderr, "measure: %d %s\n", st, st ? dqmc_last_error() : "");
+  std::vector<int8_t> fo((size_t)n_chains * L * n);
+  dqmc_get_fields(b, fo.data(), nullptr);
+  writef(dir + "/obs.bin", obs.data(), obs.size());
+  writef(dir + "/green.bin", green.data(), green.size());
+  writef(dir + "/fields_out.bin", fo.data(), fo.size());
+  dqmc_destroy(b);
+  std::free(w);
+  return 0;
+}

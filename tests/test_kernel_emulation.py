@@ -1,0 +1,136 @@
+"""The kernel sources run on the CPU through the test-only host emulation (tests/emu): the C ABI,
+the N <= 64 register/LDS sweep kernel, the initialisation, constants and measurement kernels and
+the workspace kernels execute work-item by work-item with the wavefront collectives emulated.
+
+* parity: fields after the sweeps equal the oracle's bit for bit and G(0) agrees to 1e-10
+  (square 4x4 over two sweeps, square 8x8 and honeycomb 6x6 over one), as on the GPU;
+* FP32 wraps: chains stay at half filling with drift of the FP32 order;
+* continuous batching: requests served through slot re-initialisation and per-chain sweep counts
+  give bit for bit the result of the same request alone;
+* with DQMC_EMU_SANITIZERS=1 the same runs under AddressSanitizer (no access outside any
+  buffer: workspace, LDS, stacks) and ThreadSanitizer (no two work-items touch the same LDS or
+  workspace location without a barrier ordering them).
+
+The GPU is not involved; the package never loads this build.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import dqmc_inputs as di
+
+from emu import build as emu_build  # noqa: E402  (tests/ is on sys.path)
+
+if emu_build.compiler() is None:
+    pytest.skip("clang++ not available", allow_module_level=True)
+
+SANITIZERS = os.environ.get("DQMC_EMU_SANITIZERS") == "1"
+
+
+@pytest.fixture(scope="module")
+def plain():
+    return emu_build.build("plain")
+
+
+def _write_case(d, w, n, sweeps, precision, refresh, drift_limit, first=0):
+    d.mkdir(parents=True, exist_ok=True)
+    (d / "header.txt").write_text(
+        f"{w.n_sites} {w.n_slices} {w.stab_every} {1 if precision == 'fp32' else 0} {refresh} 0 "
+        f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n")
+    np.asarray(w.hopping(), dtype=np.float64).tofile(d / "hop.bin")
+    np.asarray(w.fields(n, first), dtype=np.int8).tofile(d / "fields.bin")
+    np.asarray(w.seeds(n, first), dtype=np.uint64).tofile(d / "seeds.bin")
+
+
+def _run(exe, d, timeout=1800, env=None):
+    r = subprocess.run([exe, str(d)], capture_output=True, text=True, timeout=timeout,
+                       env=dict(os.environ, **(env or {})))
+    assert r.returncode == 0, r.stderr[-3000:]
+    return r.stderr
+
+
+def _outputs(d, w, n):
+    from paper_2106_00712_amd.dqmc import OBS_DTYPE
+    N, L = w.n_sites, w.n_slices
+    obs = np.fromfile(d / "obs.bin", dtype=OBS_DTYPE)
+    green = np.fromfile(d / "green.bin", dtype=np.float64).reshape(n, 2, N, N)
+    fields = np.fromfile(d / "fields_out.bin", dtype=np.int8).reshape(n, L, N)
+    return obs, green, fields
+
+
+@pytest.mark.parametrize("name,n,sweeps,variant", [
+    ("square4x4_U4_b2", 1, 2, 2),
+    ("square8x8_U4_b4", 1, 1, 2),
+    ("honeycomb6x6_U3_b6", 1, 1, 1),
+])
+def test_emulated_sweeps_match_oracle(plain, tmp_path, name, n, sweeps, variant):
+    from oracle import Model, OracleChains
+    w = di.WORKLOADS[name]
+    _write_case(tmp_path, w, n, sweeps, "fp64", 0, 0.0)
+    log = _run(plain["run_chains"], tmp_path)
+    assert f"variant {variant}" in log, log
+    obs, green, fields = _outputs(tmp_path, w, n)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), w.fields(n), w.seeds(n))
+    oc.sweep(sweeps)
+    om = oc.measure()
+    for c in range(n):
+        if om[c]["near_ties"] or obs["near_ties"][c]:
+            continue
+        assert np.array_equal(fields[c], oc.fields()[c]), (name, c)
+        ref = oc.green()[c]
+        assert np.max(np.abs(green[c] - ref)) / max(1.0, np.max(np.abs(ref))) < 1e-10
+        assert abs(obs["double_occ"][c] - om[c]["double_occ"]) < 1e-10
+        assert obs["accepted"][c] == om[c]["accepted"]
+    assert not np.any(obs["flags"])
+
+
+def test_emulated_fp32_chains_are_sound(plain, tmp_path):
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    _write_case(tmp_path, w, 2, 2, "fp32", 3, 1e-3)
+    _run(plain["run_chains"], tmp_path)
+    obs, _, _ = _outputs(tmp_path, w, 2)
+    assert not np.any(obs["flags"])
+    assert np.all(np.abs(obs["density"] - 1.0) < 1e-9)
+    assert np.all(obs["max_drift"] < 1e-4)
+    assert np.all(obs["sweeps_done"] == 2)
+
+
+@pytest.mark.parametrize("fill", ["0x00", "0xff", "-1"])
+def test_emulated_results_do_not_depend_on_initial_memory(plain, tmp_path, fill):
+    """Neither the LDS nor the workspace is read before it is written: other starting bytes
+    (zeros, NaN patterns, pseudo-random) give the same bits."""
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    outs = []
+    for tag, env in (("ref", {}), ("alt", {"EMU_LDS_FILL": fill, "EMU_WS_FILL": fill if fill != "-1" else "0x5a"})):
+        d = tmp_path / tag
+        _write_case(d, w, 1, 2, "fp32", 3, 1.0)
+        _run(plain["run_chains"], d, env=env)
+        outs.append([(d / f).read_bytes() for f in ("obs.bin", "green.bin", "fields_out.bin")])
+    assert outs[0] == outs[1]
+
+
+def test_emulated_serving_same_alone_and_in_the_mix(plain):
+    """FP32 wraps, 4x4 at beta = 1: 8 requests through 3 slots, 2 sweeps per launch."""
+    r = subprocess.run([plain["serve_chains"], "4", "1.0", "1", "3", "8", "3", "2"], capture_output=True,
+                       text=True, timeout=1800)
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
+    assert r.stdout.count("same") == 8
+
+
+@pytest.mark.skipif(not SANITIZERS, reason="set DQMC_EMU_SANITIZERS=1 (builds two sanitizer variants, minutes)")
+@pytest.mark.parametrize("sanitizer", ["asan", "tsan"])
+def test_emulated_kernels_under_sanitizers(tmp_path, sanitizer):
+    exes = emu_build.build(sanitizer)
+    env = {"TSAN_OPTIONS": "halt_on_error=1 exitcode=66", "ASAN_OPTIONS": "detect_leaks=0"}
+    cases = [("square4x4_U4_b2", "fp64", 0, 2), ("square4x4_U4_b2", "fp32", 3, 2),
+             ("square8x8_U4_b4", "fp64", 0, 1), ("square8x8_U4_b4", "fp32", 3, 1)]
+    for name, precision, refresh, sweeps in cases:
+        d = tmp_path / f"{name}_{precision}"
+        _write_case(d, di.WORKLOADS[name], 1, sweeps, precision, refresh, 1.0)
+        log = _run(exes["run_chains"], d, timeout=3600, env=env)
+        assert "Sanitizer" not in log, (name, precision, log[-3000:])
+    r = subprocess.run([exes["serve_chains"], "4", "1.0", "1", "3", "6", "3", "2"], capture_output=True,
+                       text=True, timeout=3600, env=dict(os.environ, **env))
+    assert r.returncode == 0 and "Sanitizer" not in r.stderr, r.stderr[-3000:]
