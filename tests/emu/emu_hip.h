@@ -68,12 +68,16 @@ struct Barrier {
   }
 };
 
+// Exchange buffers of the wavefront collectives, double-buffered: collective k uses buffer k % 2,
+// so one barrier per collective suffices (a lane can only reach collective k + 2, which writes
+// buffer k % 2 again, after every lane has passed collective k + 1, i.e. finished reading k).
 struct Wave {
   Barrier bar;
   int size = 64;
-  uint64_t slot[64];
-  double a64[64], b64[64];
-  float a32[64], b32[64];
+  int seq[64] = {};
+  uint64_t slot[2][64];
+  double a64[2][64], b64[2][64];
+  float a32[2][64], b32[2][64];
 };
 
 struct Block {
@@ -109,13 +113,15 @@ inline T from_bits(uint64_t u) {
 }
 
 // all lanes publish a value; returns a copy of the wave's 64 values
+inline int next_buffer(Wave& w) { return w.seq[lane_id()]++ & 1; }
+
 template <typename T>
 inline void gather(T v, uint64_t out[64]) {
   Wave& w = my_wave();
-  w.slot[lane_id()] = to_bits(v);
+  const int q = next_buffer(w);
+  w.slot[q][lane_id()] = to_bits(v);
   w.bar.wait("gather");
-  std::memcpy(out, w.slot, sizeof(uint64_t) * 64);
-  w.bar.wait("gather end");
+  std::memcpy(out, w.slot[q], sizeof(uint64_t) * 64);
 }
 
 template <typename T>
@@ -175,34 +181,32 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // of lane l holds row 4v + l/16, FP32 output register v holds row 4(l/16) + v, column l%16.
 inline d4v mfma_f64(double a, double b, d4v c) {
   Wave& w = my_wave();
-  const int l = lane_id();
-  w.a64[l] = a;
-  w.b64[l] = b;
+  const int l = lane_id(), q = next_buffer(w);
+  w.a64[q][l] = a;
+  w.b64[q][l] = b;
   w.bar.wait("mfma");
   d4v out;
   for (int v = 0; v < 4; ++v) {
     const int row = 4 * v + (l >> 4), col = l & 15;
     double s = c[v];
-    for (int k = 0; k < 4; ++k) s = std::fma(w.a64[16 * k + row], w.b64[16 * k + col], s);
+    for (int k = 0; k < 4; ++k) s = std::fma(w.a64[q][16 * k + row], w.b64[q][16 * k + col], s);
     out[v] = s;
   }
-  w.bar.wait("mfma end");
   return out;
 }
 inline f4v mfma_f32(float a, float b, f4v c) {
   Wave& w = my_wave();
-  const int l = lane_id();
-  w.a32[l] = a;
-  w.b32[l] = b;
+  const int l = lane_id(), q = next_buffer(w);
+  w.a32[q][l] = a;
+  w.b32[q][l] = b;
   w.bar.wait("mfma32");
   f4v out;
   for (int v = 0; v < 4; ++v) {
     const int row = 4 * (l >> 4) + v, col = l & 15;
     float s = c[v];
-    for (int k = 0; k < 4; ++k) s = std::fma(w.a32[16 * k + row], w.b32[16 * k + col], s);
+    for (int k = 0; k < 4; ++k) s = std::fma(w.a32[q][16 * k + row], w.b32[q][16 * k + col], s);
     out[v] = s;
   }
-  w.bar.wait("mfma32 end");
   return out;
 }
 

@@ -3,7 +3,7 @@
 // sweep counts (dqmc_sweep_counts) in a batch of CAPACITY chains, TICK sweeps per launch; each
 // result is then compared bit for bit with the same request run alone.  Exit status 3 if any
 // differs.
-// usage: serve_chains L BETA PREC(0|1) REFRESH N_REQ CAPACITY TICK
+// usage: serve_chains L BETA PREC(0|1) REFRESH N_REQ CAPACITY TICK [MAX_SWEEPS]
 #include "emu_hip.h"
 #include "dqmc.h"
 #include "dqmc_device.hpp"
@@ -48,6 +48,7 @@ int main(int argc, char** argv) {
   for (int r = 0; r < n_req; ++r) {
     seeds[r] = 0x5EED0000ull + 977 * r;
     sweeps[r] = 2 + (r * 5) % 8;
+    if (argc > 8) sweeps[r] = std::min(sweeps[r], std::atoi(argv[8]));
   }
   auto run_batch = [&](int nc, const uint64_t* sd, char** wout, dqmc_batch** bout) {
     const size_t ws = dqmc_workspace_bytes(&m, nc);

@@ -111,12 +111,16 @@ def test_emulated_results_do_not_depend_on_initial_memory(plain, tmp_path, fill)
     assert outs[0] == outs[1]
 
 
-def test_emulated_serving_same_alone_and_in_the_mix(plain):
-    """FP32 wraps, 4x4 at beta = 1: 8 requests through 3 slots, 2 sweeps per launch."""
-    r = subprocess.run([plain["serve_chains"], "4", "1.0", "1", "3", "8", "3", "2"], capture_output=True,
-                       text=True, timeout=1800)
+@pytest.mark.parametrize("args,n_req", [
+    (("4", "1.0", "1", "3", "8", "3", "2"), 8),         # FP32 wraps, register/LDS kernel
+    (("10", "0.5", "0", "0", "3", "2", "2", "4"), 3),   # FP64, workspace kernel (N = 100)
+])
+def test_emulated_serving_same_alone_and_in_the_mix(plain, args, n_req):
+    """Requests served through slot re-initialisation and per-chain sweep counts (L, beta,
+    precision, refresh, requests, slots, sweeps per launch[, most sweeps per request])."""
+    r = subprocess.run([plain["serve_chains"], *args], capture_output=True, text=True, timeout=1800)
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
-    assert r.stdout.count("same") == 8
+    assert r.stdout.count(": same") == n_req
 
 
 @pytest.mark.skipif(not SANITIZERS, reason="set DQMC_EMU_SANITIZERS=1 (builds two sanitizer variants, minutes)")
@@ -131,6 +135,10 @@ def test_emulated_kernels_under_sanitizers(tmp_path, sanitizer):
         _write_case(d, di.WORKLOADS[name], 1, sweeps, precision, refresh, 1.0)
         log = _run(exes["run_chains"], d, timeout=3600, env=env)
         assert "Sanitizer" not in log, (name, precision, log[-3000:])
-    r = subprocess.run([exes["serve_chains"], "4", "1.0", "1", "3", "6", "3", "2"], capture_output=True,
-                       text=True, timeout=3600, env=dict(os.environ, **env))
-    assert r.returncode == 0 and "Sanitizer" not in r.stderr, r.stderr[-3000:]
+    serve = [("4", "1.0", "1", "3", "6", "3", "2")]
+    if sanitizer == "asan":
+        serve.append(("10", "0.5", "1", "3", "3", "2", "2", "4"))   # FP32, workspace kernel
+    for args in serve:
+        r = subprocess.run([exes["serve_chains"], *args], capture_output=True, text=True, timeout=3600,
+                           env=dict(os.environ, **env))
+        assert r.returncode == 0 and "Sanitizer" not in r.stderr, (args, r.stderr[-3000:])
