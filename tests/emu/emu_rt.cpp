@@ -131,7 +131,7 @@ extern "C" __attribute__((no_sanitize("thread"))) void emu_trampoline() {
 
 __attribute__((no_sanitize("thread"))) static void run_block(Block& blk, unsigned b, const std::function<void()>& body) {
   const int nt = blk.nthreads;
-  const size_t ss = 512 * 1024;
+  const size_t ss = 8u << 20;   // sanitizer builds inline the kernels into frames of several hundred KB
   std::vector<Fiber> fs(nt);
   for (int t = 0; t < nt; ++t) {
     Fiber& f = fs[t];
