@@ -1,6 +1,6 @@
 """Builds the test-only host emulation of the library (emu_hip.h): the library's sources, with the
 few device-only constructs rewritten, compiled for the host with clang++ together with the fiber
-runtime and two drivers (run_chains, serve_chains).
+runtime and three drivers (run_chains, serve_chains, ising_chains).
 
 Rewrites (applied to copies under tests/emu/_build/<variant>/src, never to the sources):
   * the dynamic LDS declaration becomes the emulated workgroup's LDS buffer;
@@ -28,6 +28,8 @@ FLAGS = {
     "tsan": ["-O1", "-g", "-fsanitize=thread", "-DEMU_TSAN"],
 }
 
+DRIVERS = ("run_chains", "serve_chains", "ising_chains")
+
 REWRITES = [
     (re.compile(r"extern __shared__ double lds\[\];"), "double* lds = emu::dyn_lds();"),
     (re.compile(r'asm volatile\("s_waitcnt lgkmcnt\(0\)" ::: "memory"\);'), "emu::wave_sync();"),
@@ -47,7 +49,7 @@ def compiler():
 def _sources():
     files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")) +
                    glob.glob(os.path.join(INCLUDE, "*.h")))
-    return [f for f in files if os.path.basename(f) != "ising.hip"]
+    return files
 
 
 def _digest(variant):
@@ -72,12 +74,12 @@ def _copy_sources(dst):
 
 
 def build(variant="plain"):
-    """Returns {'run_chains': path, 'serve_chains': path} for the variant, building if needed."""
+    """Returns {driver name: executable path} for the variant, building if needed."""
     cxx = compiler()
     if cxx is None:
         raise RuntimeError("clang++ not found")
     out = os.path.join(HERE, "_build", variant)
-    exes = {k: os.path.join(out, k) for k in ("run_chains", "serve_chains")}
+    exes = {k: os.path.join(out, k) for k in DRIVERS}
     stamp = os.path.join(out, "stamp")
     dig = _digest(variant)
     if all(os.path.exists(p) for p in exes.values()) and os.path.exists(stamp) and open(stamp).read() == dig:
@@ -90,7 +92,7 @@ def build(variant="plain"):
     for f in sorted(glob.glob(os.path.join(src, "*.hip"))):
         jobs.append([cxx, "-std=c++17", *flags, "-w", "-I", HERE, "-I", src, "-x", "c++", "-c", f,
                      "-o", f[:-4] + ".o"])
-    for name in ("emu_rt", "run_chains", "serve_chains"):
+    for name in ("emu_rt",) + DRIVERS:
         jobs.append([cxx, "-std=c++17", *flags, "-w", "-I", HERE, "-I", src, "-c",
                      os.path.join(HERE, name + ".cpp"), "-o", os.path.join(out, name + ".obj")])
 

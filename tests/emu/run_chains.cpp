@@ -3,6 +3,10 @@
 // one-sweep dqmc_sweep calls, dqmc_measure and dqmc_get_fields, and writes obs.bin, green.bin and
 // fields_out.bin to DIR.  The workspace is one exact-size heap block, so AddressSanitizer sees
 // any access past it; EMU_WS_FILL and EMU_LDS_FILL set the bytes the workspace and LDS start with.
+// An optional second line of header.txt, "sweep_mode series static", selects the sweep mode
+// (dqmc_model.sweep_mode), dqmc_sweep_series in place of the one-sweep calls (series.bin,
+// [n_sweeps][n_chains][4]), or the allocation-free dqmc_run_static in place of the whole
+// sequence.
 // usage: run_chains DIR
 #include "emu_hip.h"
 #include "dqmc.h"
@@ -35,6 +39,8 @@ int main(int argc, char** argv) {
   double drift, U, dtau;
   if (std::fscanf(h, "%d %d %d %d %d %d %lf %lf %lf %d %d %d", &n, &L, &stab, &prec, &refresh, &k, &drift, &U,
                   &dtau, &n_chains, &n_sweeps, &have_fields) != 12) return 2;
+  int sweep_mode = 0, use_series = 0, use_static = 0;
+  if (std::fscanf(h, "%d %d %d", &sweep_mode, &use_series, &use_static) != 3) sweep_mode = use_series = use_static = 0;
   std::fclose(h);
   auto hop = readf<double>(dir + "/hop.bin", (size_t)n * n);
   auto seeds = readf<uint64_t>(dir + "/seeds.bin", n_chains);
@@ -44,6 +50,20 @@ int main(int argc, char** argv) {
   m.n_sites = n; m.hopping = hop.data(); m.U = U; m.mu = 0.0; m.dtau = dtau; m.n_slices = L;
   m.stab_every = stab; m.refresh_every = refresh; m.delay_rank = k;
   m.precision = prec ? DQMC_FP32_WRAP : DQMC_FP64; m.drift_limit = drift;
+  m.sweep_mode = sweep_mode;
+  if (use_static) {
+    std::vector<dqmc_obs> obs(n_chains);
+    std::vector<double> green((size_t)n_chains * 2 * n * n);
+    std::vector<int8_t> fo((size_t)n_chains * L * n);
+    int st = dqmc_run_static(&m, n_chains, have_fields ? fields.data() : nullptr, seeds.data(), n_sweeps,
+                             obs.data(), green.data(), fo.data(), nullptr);
+    std::fprintf(stderr, "run_static: %d %s\n", st, st ? dqmc_last_error() : "");
+    if (st != DQMC_OK && st != DQMC_ENUMERIC) return 1;
+    writef(dir + "/obs.bin", obs.data(), obs.size());
+    writef(dir + "/green.bin", green.data(), green.size());
+    writef(dir + "/fields_out.bin", fo.data(), fo.size());
+    return 0;
+  }
   const size_t ws = dqmc_workspace_bytes(&m, n_chains);
   char* w = (char*)std::aligned_alloc(256, (ws + 255) & ~(size_t)255);
   const char* wf = std::getenv("EMU_WS_FILL");
@@ -55,9 +75,16 @@ int main(int argc, char** argv) {
   int kk, ss, lds, var;
   dqmc_batch_info(b, &kk, &ss, &lds, &var);
   std::fprintf(stderr, "k %d stab %d lds %d variant %d\n", kk, ss, lds, var);
-  for (int s = 0; s < n_sweeps; ++s) {
-    st = dqmc_sweep(b, 1, nullptr);
-    std::fprintf(stderr, "sweep %d: %d\n", s, st);
+  if (use_series) {
+    std::vector<double> series((size_t)n_sweeps * n_chains * DQMC_SERIES_WIDTH);
+    st = dqmc_sweep_series(b, n_sweeps, nullptr, series.data(), nullptr);
+    std::fprintf(stderr, "sweep_series: %d\n", st);
+    writef(dir + "/series.bin", series.data(), series.size());
+  } else {
+    for (int s = 0; s < n_sweeps; ++s) {
+      st = dqmc_sweep(b, 1, nullptr);
+      std::fprintf(stderr, "sweep %d: %d\n", s, st);
+    }
   }
   std::vector<dqmc_obs> obs(n_chains);
   std::vector<double> green((size_t)n_chains * 2 * n * n);

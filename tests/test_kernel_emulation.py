@@ -7,6 +7,8 @@ the workspace kernels execute work-item by work-item with the wavefront collecti
 * FP32 wraps: chains stay at half filling with drift of the FP32 order;
 * continuous batching: requests served through slot re-initialisation and per-chain sweep counts
   give bit for bit the result of the same request alone;
+* sweep modes and the per-sweep series against the oracle, the allocation-free entry point
+  against the workspace path, the Ising sweep against its oracle bit for bit;
 * with DQMC_EMU_SANITIZERS=1 the same runs under AddressSanitizer (no access outside any
   buffer: workspace, LDS, stacks) and ThreadSanitizer (no two work-items touch the same LDS or
   workspace location without a barrier ordering them).
@@ -34,11 +36,12 @@ def plain():
     return emu_build.build("plain")
 
 
-def _write_case(d, w, n, sweeps, precision, refresh, drift_limit, first=0):
+def _write_case(d, w, n, sweeps, precision, refresh, drift_limit, first=0, sweep_mode=0, series=0,
+                static=0):
     d.mkdir(parents=True, exist_ok=True)
     (d / "header.txt").write_text(
         f"{w.n_sites} {w.n_slices} {w.stab_every} {1 if precision == 'fp32' else 0} {refresh} 0 "
-        f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n")
+        f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n{sweep_mode} {series} {static}\n")
     np.asarray(w.hopping(), dtype=np.float64).tofile(d / "hop.bin")
     np.asarray(w.fields(n, first), dtype=np.int8).tofile(d / "fields.bin")
     np.asarray(w.seeds(n, first), dtype=np.uint64).tofile(d / "seeds.bin")
@@ -84,6 +87,66 @@ def test_emulated_sweeps_match_oracle(plain, tmp_path, name, n, sweeps, variant)
         assert abs(obs["double_occ"][c] - om[c]["double_occ"]) < 1e-10
         assert obs["accepted"][c] == om[c]["accepted"]
     assert not np.any(obs["flags"])
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_emulated_sweep_modes_and_series_match_oracle(plain, tmp_path, mode):
+    """Alternating up/down sweeps (bit 0) and per-slice estimators (bit 1) run in the workspace
+    kernels at any N; the per-sweep series (dqmc_sweep_series) against the oracle's per-sweep
+    measurements, the fields bit for bit."""
+    from oracle import Model, OracleChains
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    n, sweeps = 2, 3
+    _write_case(tmp_path, w, n, sweeps, "fp64", 0, 0.0, sweep_mode=mode, series=1)
+    _run(plain["run_chains"], tmp_path)
+    obs, _, fields = _outputs(tmp_path, w, n)
+    ser = np.fromfile(tmp_path / "series.bin", dtype=np.float64).reshape(sweeps, n, 4)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, sweep_mode=mode),
+                      w.fields(n), w.seeds(n))
+    for k in range(sweeps):
+        oc.sweep(1)
+        ref = oc.measure()
+        for c in range(n):
+            want = [ref[c]["double_occ"], ref[c]["density"], ref[c]["kinetic"]]
+            assert np.max(np.abs(ser[k, c, :3] - want)) < 1e-9, (k, c)
+            assert ser[k, c, 3] == 0.0
+    assert np.array_equal(fields, oc.fields())
+    if mode & 2:
+        ref = oc.measure()
+        for c in range(n):
+            assert abs(obs["slice_double_occ"][c] - ref[c]["slice_double_occ"]) < 1e-9
+
+
+def test_emulated_static_entry_equals_workspace_path(plain, tmp_path):
+    """dqmc_run_static (the allocation-free entry point) gives the bits of the workspace path."""
+    w = di.WORKLOADS["square4x4_U4_b2"]
+    outs = []
+    for static in (0, 1):
+        d = tmp_path / f"s{static}"
+        _write_case(d, w, 3, 2, "fp64", 0, 0.0, static=static)
+        _run(plain["run_chains"], d)
+        outs.append([(d / f).read_bytes() for f in ("obs.bin", "green.bin", "fields_out.bin")])
+    assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("L,n,sweeps,T", [(2, 3, 20, 2.269), (6, 3, 10, 2.269), (16, 2, 5, 2.269)])
+def test_emulated_ising_matches_oracle(plain, tmp_path, L, n, sweeps, T):
+    from oracle.ising_oracle import IsingChains
+    from paper_2106_00712_amd.ising import ISING_OBS_DTYPE
+    seeds = di.chain_seeds(7, n, L)
+    np.asarray(seeds, dtype=np.uint64).tofile(tmp_path / "seeds.bin")
+    r = subprocess.run([plain["ising_chains"], str(tmp_path), str(L), str(T), str(n), str(sweeps)],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    spins = np.fromfile(tmp_path / "spins.bin", dtype=np.int8).reshape(n, L * L)
+    ser = np.fromfile(tmp_path / "series.bin", dtype=np.int32).reshape(n, sweeps, 2)
+    st = np.fromfile(tmp_path / "stats.bin", dtype=ISING_OBS_DTYPE)
+    oc = IsingChains(L, 1.0, T, None, seeds)
+    ref = oc.sweep(sweeps)
+    assert np.array_equal(spins, oc.spins())
+    assert np.array_equal(ser, ref)
+    for c in range(n):
+        assert st["accepted"][c] == oc.accepted[c] and st["sum_bond"][c] == oc.sum_b[c]
 
 
 def test_emulated_fp32_chains_are_sound(plain, tmp_path):
