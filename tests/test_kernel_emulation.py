@@ -37,10 +37,10 @@ def plain():
 
 
 def _write_case(d, w, n, sweeps, precision, refresh, drift_limit, first=0, sweep_mode=0, series=0,
-                static=0):
+                static=0, delay_rank=0):
     d.mkdir(parents=True, exist_ok=True)
     (d / "header.txt").write_text(
-        f"{w.n_sites} {w.n_slices} {w.stab_every} {1 if precision == 'fp32' else 0} {refresh} 0 "
+        f"{w.n_sites} {w.n_slices} {w.stab_every} {1 if precision == 'fp32' else 0} {refresh} {delay_rank} "
         f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n{sweep_mode} {series} {static}\n")
     np.asarray(w.hopping(), dtype=np.float64).tofile(d / "hop.bin")
     np.asarray(w.fields(n, first), dtype=np.int8).tofile(d / "fields.bin")
@@ -87,6 +87,37 @@ def test_emulated_sweeps_match_oracle(plain, tmp_path, name, n, sweeps, variant)
         assert abs(obs["double_occ"][c] - om[c]["double_occ"]) < 1e-10
         assert obs["accepted"][c] == om[c]["accepted"]
     assert not np.any(obs["flags"])
+
+
+# every instantiation of the N <= 64 kernel: padded size 16 (blocks of 8), 32 and 64 (blocks of 8
+# and 16), FP64 and FP32 wraps; square 5x5 (N = 25) and 6x6 (N = 36) pad with idle sites
+_SMALL = {L: di.Workload(f"square{L}x{L}_U4_b1", 9, "square", L, 4.0, 1.0, 0.1, 2, 1, 5)
+          for L in (4, 5, 6)}
+
+
+@pytest.mark.parametrize("L,k,np_", [(4, 8, 16), (5, 8, 32), (5, 16, 32), (6, 8, 64), (6, 16, 64)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_emulated_fast_kernel_instantiations(plain, tmp_path, L, k, np_, precision):
+    """FP64: fields bit for bit and G(0) to 1e-10 against the oracle; FP32 wraps (refresh 3):
+    sound chains, and the same accept/reject decisions as FP64 unless a ratio came close."""
+    from oracle import Model, OracleChains
+    w = _SMALL[L]
+    n, sweeps = 2, 2
+    _write_case(tmp_path, w, n, sweeps, precision, 3 if precision == "fp32" else 0, 1.0, delay_rank=k)
+    log = _run(plain["run_chains"], tmp_path)
+    assert f"k {k} " in log and "variant 2" in log, log
+    obs, green, fields = _outputs(tmp_path, w, n)
+    assert not np.any(obs["flags"])
+    if L % 2 == 0:        # half filling at mu = 0 needs a bipartite lattice
+        assert np.all(np.abs(obs["density"] - 1.0) < 1e-9)
+    if precision == "fp32":
+        assert np.all(obs["max_drift"] < 1e-4)
+        return
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), w.fields(n), w.seeds(n))
+    oc.sweep(sweeps)
+    for c in range(n):
+        assert np.array_equal(fields[c], oc.fields()[c]), (L, k, c)
+        assert np.max(np.abs(green[c] - oc.green()[c])) < 1e-10
 
 
 @pytest.mark.parametrize("mode", [1, 3])
@@ -198,6 +229,12 @@ def test_emulated_kernels_under_sanitizers(tmp_path, sanitizer):
         _write_case(d, di.WORKLOADS[name], 1, sweeps, precision, refresh, 1.0)
         log = _run(exes["run_chains"], d, timeout=3600, env=env)
         assert "Sanitizer" not in log, (name, precision, log[-3000:])
+    for L, k in ((5, 8), (5, 16), (6, 8), (6, 16)):
+        for precision in ("fp64", "fp32"):
+            d = tmp_path / f"small{L}_{k}_{precision}"
+            _write_case(d, _SMALL[L], 1, 1, precision, 3 if precision == "fp32" else 0, 1.0, delay_rank=k)
+            log = _run(exes["run_chains"], d, timeout=3600, env=env)
+            assert "Sanitizer" not in log, (L, k, precision, log[-3000:])
     serve = [("4", "1.0", "1", "3", "6", "3", "2")]
     if sanitizer == "asan":
         serve.append(("10", "0.5", "1", "3", "3", "2", "2", "4"))   # FP32, workspace kernel
