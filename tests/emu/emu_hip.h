@@ -174,6 +174,12 @@ inline int update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, b
   return from_bits<int>(all[s]);
 }
 
+// MFMA instructions issued (one per wavefront), FP64 and FP32: work counters of the emulation.
+inline long long& mfma_issued(int fp32) {
+  static long long n[2] = {0, 0};
+  return n[fp32];
+}
+
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -182,6 +188,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 inline d4v mfma_f64(double a, double b, d4v c) {
   Wave& w = my_wave();
   const int l = lane_id(), q = next_buffer(w);
+  if (l == 0) ++mfma_issued(0);
   w.a64[q][l] = a;
   w.b64[q][l] = b;
   w.bar.wait("mfma");
@@ -197,6 +204,7 @@ inline d4v mfma_f64(double a, double b, d4v c) {
 inline f4v mfma_f32(float a, float b, f4v c) {
   Wave& w = my_wave();
   const int l = lane_id(), q = next_buffer(w);
+  if (l == 0) ++mfma_issued(1);
   w.a32[q][l] = a;
   w.b32[q][l] = b;
   w.bar.wait("mfma32");

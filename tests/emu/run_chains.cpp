@@ -75,6 +75,7 @@ int main(int argc, char** argv) {
   int kk, ss, lds, var;
   dqmc_batch_info(b, &kk, &ss, &lds, &var);
   std::fprintf(stderr, "k %d stab %d lds %d variant %d\n", kk, ss, lds, var);
+  const long long m64_init = emu::mfma_issued(0), m32_init = emu::mfma_issued(1);
   if (use_series) {
     std::vector<double> series((size_t)n_sweeps * n_chains * DQMC_SERIES_WIDTH);
     st = dqmc_sweep_series(b, n_sweeps, nullptr, series.data(), nullptr);
@@ -86,6 +87,8 @@ int main(int argc, char** argv) {
       std::fprintf(stderr, "sweep %d: %d\n", s, st);
     }
   }
+  std::fprintf(stderr, "mfma issued in the sweeps: fp64 %lld fp32 %lld (init: fp64 %lld fp32 %lld)\n",
+               emu::mfma_issued(0) - m64_init, emu::mfma_issued(1) - m32_init, m64_init, m32_init);
   std::vector<dqmc_obs> obs(n_chains);
   std::vector<double> green((size_t)n_chains * 2 * n * n);
   st = dqmc_measure(b, obs.data(), green.data(), nullptr);
