@@ -6,7 +6,8 @@
 // An optional second line of header.txt, "sweep_mode series static", selects the sweep mode
 // (dqmc_model.sweep_mode), dqmc_sweep_series in place of the one-sweep calls (series.bin,
 // [n_sweeps][n_chains][4]), or the allocation-free dqmc_run_static in place of the whole
-// sequence.
+// sequence.  An optional third line "slice n_wraps" adds the fixed-field probe
+// dqmc_debug_green(slice, n_wraps) right after the initialisation (probe.bin, [n_chains][2][N][N]).
 // usage: run_chains DIR
 #include "emu_hip.h"
 #include "dqmc.h"
@@ -41,6 +42,8 @@ int main(int argc, char** argv) {
                   &dtau, &n_chains, &n_sweeps, &have_fields) != 12) return 2;
   int sweep_mode = 0, use_series = 0, use_static = 0;
   if (std::fscanf(h, "%d %d %d", &sweep_mode, &use_series, &use_static) != 3) sweep_mode = use_series = use_static = 0;
+  int probe_slice = -1, probe_wraps = 0;
+  if (std::fscanf(h, "%d %d", &probe_slice, &probe_wraps) != 2) probe_slice = -1;
   std::fclose(h);
   auto hop = readf<double>(dir + "/hop.bin", (size_t)n * n);
   auto seeds = readf<uint64_t>(dir + "/seeds.bin", n_chains);
@@ -75,6 +78,13 @@ int main(int argc, char** argv) {
   int kk, ss, lds, var;
   dqmc_batch_info(b, &kk, &ss, &lds, &var);
   std::fprintf(stderr, "k %d stab %d lds %d variant %d\n", kk, ss, lds, var);
+  if (probe_slice >= 0) {
+    std::vector<double> g((size_t)n_chains * 2 * n * n);
+    st = dqmc_debug_green(b, probe_slice, probe_wraps, g.data(), nullptr);
+    std::fprintf(stderr, "debug_green(%d, %d): %d\n", probe_slice, probe_wraps, st);
+    if (st) return 1;
+    writef(dir + "/probe.bin", g.data(), g.size());
+  }
   const long long m64_init = emu::mfma_issued(0), m32_init = emu::mfma_issued(1);
   if (use_series) {
     std::vector<double> series((size_t)n_sweeps * n_chains * DQMC_SERIES_WIDTH);

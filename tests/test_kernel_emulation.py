@@ -37,11 +37,12 @@ def plain():
 
 
 def _write_case(d, w, n, sweeps, precision, refresh, drift_limit, first=0, sweep_mode=0, series=0,
-                static=0, delay_rank=0):
+                static=0, delay_rank=0, probe=None):
     d.mkdir(parents=True, exist_ok=True)
     (d / "header.txt").write_text(
         f"{w.n_sites} {w.n_slices} {w.stab_every} {1 if precision == 'fp32' else 0} {refresh} {delay_rank} "
-        f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n{sweep_mode} {series} {static}\n")
+        f"{drift_limit} {w.U} {w.dtau} {n} {sweeps} 1\n{sweep_mode} {series} {static}\n" +
+        (f"{probe[0]} {probe[1]}\n" if probe else ""))
     np.asarray(w.hopping(), dtype=np.float64).tofile(d / "hop.bin")
     np.asarray(w.fields(n, first), dtype=np.int8).tofile(d / "fields.bin")
     np.asarray(w.seeds(n, first), dtype=np.uint64).tofile(d / "seeds.bin")
@@ -118,6 +119,26 @@ def test_emulated_fast_kernel_instantiations(plain, tmp_path, L, k, np_, precisi
     for c in range(n):
         assert np.array_equal(fields[c], oc.fields()[c]), (L, k, c)
         assert np.max(np.abs(green[c] - oc.green()[c])) < 1e-10
+
+
+def test_emulated_fp32_wraps_within_bound_at_the_tuned_refresh(plain, tmp_path):
+    """Honeycomb 6x6 (N = 72, the FP32 workspace kernel), U = 3, beta = 6: r* = 5 FP32 wraps from
+    the fresh FP64 G stay within 1e-5 of the oracle's fresh G, on chains the refresh was not
+    tuned on (the GPU check of this lattice is off, see the FP32 GPU tests).  The emulated FP32
+    MFMA accumulates with one float fma per k-step; the matrix cores may round differently, so
+    this checks the kernel's arithmetic, not the device's last bits."""
+    from oracle import Model, OracleChains
+    w = di.WORKLOADS["honeycomb6x6_U3_b6"]
+    n, r, first = 2, 5, 100
+    l = w.n_slices - r
+    _write_case(tmp_path, w, n, 0, "fp32", r, 1.0, first=first, probe=(l, r))
+    _run(plain["run_chains"], tmp_path)
+    g = np.fromfile(tmp_path / "probe.bin", dtype=np.float64).reshape(n, 2, w.n_sites, w.n_sites)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), w.fields(n, first),
+                      w.seeds(n, first))
+    err = float(np.max(np.abs(g - oc.debug_green(l + r, 0))))
+    print("max|dG| after", r, "FP32 wraps:", err)
+    assert err <= 1e-5
 
 
 @pytest.mark.parametrize("mode", [1, 3])
