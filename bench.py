@@ -555,7 +555,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: chains are independent, so a multi-GPU run is the "
-              "one-GPU run per device; this build launches on one GPU only.", file=sys.stderr)
+              "one-GPU run per device; bench.py launches on one GPU only.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload:

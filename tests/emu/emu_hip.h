@@ -188,7 +188,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 inline d4v mfma_f64(double a, double b, d4v c) {
   Wave& w = my_wave();
   const int l = lane_id(), q = next_buffer(w);
-  if (l == 0) ++mfma_issued(0);
+  if (l == 0) __atomic_fetch_add(&mfma_issued(0), 1, __ATOMIC_RELAXED);
   w.a64[q][l] = a;
   w.b64[q][l] = b;
   w.bar.wait("mfma");
@@ -204,7 +204,7 @@ inline d4v mfma_f64(double a, double b, d4v c) {
 inline f4v mfma_f32(float a, float b, f4v c) {
   Wave& w = my_wave();
   const int l = lane_id(), q = next_buffer(w);
-  if (l == 0) ++mfma_issued(1);
+  if (l == 0) __atomic_fetch_add(&mfma_issued(1), 1, __ATOMIC_RELAXED);
   w.a32[q][l] = a;
   w.b32[q][l] = b;
   w.bar.wait("mfma32");

@@ -1,6 +1,6 @@
 """The large-lattice workload against the oracle over a whole sweep: square 20x20 (N = 400),
-U = 8, beta = 10, dtau = 0.1 (100 slices), the products of supplement section I.2 at their most
-strongly graded in this build.  Two sampled chains of the 64-chain batch are swept once on the
+U = 8, beta = 10, dtau = 0.1 (100 slices), the most strongly graded products of supplement
+section I.2 among the workloads here.  Two sampled chains of the 64-chain batch are swept once on the
 GPU, in the batch at its full size and launch configuration, from their seeded fields, at the
 stabilisation interval the autotuner picks for this workload (5 slices: the FP64 drift stays near
 1e-7, where 10 slices reach 1e-3) and at the workload's nominal 10; the CPU oracle's results for

@@ -13,7 +13,7 @@ the workspace kernels execute work-item by work-item with the wavefront collecti
   buffer: workspace, LDS, stacks) and ThreadSanitizer (no two work-items touch the same LDS or
   workspace location without a barrier ordering them).
 
-The GPU is not involved; the package never loads this build.
+The GPU is not involved; the package never loads the emulation.
 """
 import os
 import subprocess
