@@ -74,7 +74,16 @@ def _copy_sources(dst):
 
 
 def build(variant="plain"):
-    """Returns {driver name: executable path} for the variant, building if needed."""
+    """Returns {driver name: executable path} for the variant, building if needed (one build at a
+    time per variant, across processes)."""
+    import fcntl
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    with open(os.path.join(HERE, "_build", variant + ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        return _build(variant)
+
+
+def _build(variant):
     cxx = compiler()
     if cxx is None:
         raise RuntimeError("clang++ not found")
