@@ -228,7 +228,7 @@ def test_emulated_results_do_not_depend_on_initial_memory(plain, tmp_path, fill)
 
 @pytest.mark.parametrize("args,n_req", [
     (("4", "1.0", "1", "3", "8", "3", "2"), 8),         # FP32 wraps, register/LDS kernel
-    (("10", "0.5", "0", "0", "3", "2", "2", "4"), 3),   # FP64, workspace kernel (N = 100)
+    (("10", "0.3", "0", "0", "3", "2", "2", "3"), 3),   # FP64, workspace kernel (N = 100)
 ])
 def test_emulated_serving_same_alone_and_in_the_mix(plain, args, n_req):
     """Requests served through slot re-initialisation and per-chain sweep counts (L, beta,
