@@ -1628,7 +1628,9 @@ __device__ __forceinline__ void unwrap_both(Ctx<WT>& c, int l) {
 // true G of both spins in c.gb: ratio, Philox uniform, Metropolis test, and on acceptance the
 // block's own rank-1 update and the block parts of the Sherman-Morrison vectors (x_m rows in xb,
 // y_m columns in yb, both spins), the accepted site, its two coefficients and the field flip.
-// The number accepted goes to c.cnt[0]; log|R| per spin is added to ldrun.  Run by wave 0.
+// The number accepted goes to c.cnt[(i0 / K) % 2] (two words used in turn: after a block with no
+// accepts no barrier separates the other waves' read of its count from the next block's write);
+// log|R| per spin is added to ldrun.  Run by wave 0.
 template <typename WT>
 __device__ __forceinline__ void decide_block(Ctx<WT>& c, int l, int i0, int kb, uint64_t seed,
                                              int64_t sweep, int8_t* fl, double* ldrun) {
@@ -1688,7 +1690,7 @@ __device__ __forceinline__ void decide_block(Ctx<WT>& c, int l, int i0, int kb, 
     }
   }
   if (lane == 0) {
-    c.cnt[0] = m;
+    c.cnt[(i0 / K) & 1] = m;
     ldrun[0] += ldu;
     ldrun[1] += ldd;
     if (flg) atomicOr(&c.st->flags, flg);
@@ -1756,7 +1758,7 @@ __device__ __forceinline__ void metropolis_slice(Ctx<WT>& c, int l, double* ldru
     }
     __syncthreads();
     clk.stop(c.st, PH_DECIDE);
-    const int m = c.cnt[0];
+    const int m = c.cnt[(i0 / K) & 1];
     acc_total += m;
     if (m == 0) continue;
     const int mp = (m + 3) & ~3;
@@ -1865,7 +1867,7 @@ __device__ __forceinline__ void metropolis_slice2(Ctx<WT>& c, int l, double* ldr
     }
     __syncthreads();
     clk.stop(c.st, PH_DECIDE);
-    const int m = c.cnt[0];
+    const int m = c.cnt[(i0 / K) & 1];
     acc_total += m;
     if (m > 0) {
       const int mp = (m + 3) & ~3;

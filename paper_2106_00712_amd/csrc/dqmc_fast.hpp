@@ -414,6 +414,10 @@ struct Fast {
     WT* G1 = gptr(L, 1);
     for (int i0 = 0; i0 < n; i0 += KB) {
       const int kb = min(KB, n - i0);
+      // the block's accept count alternates between two LDS words: after a block with no
+      // accepts no barrier separates the other waves' read of its count from wave 0's write of
+      // the next block's, so that write must not land on the word still being read
+      const int par = (i0 / KB) & 1;
       if (wave == 0) {
         const int sp = lane >> 5, q = lane & 31, cc = q % KB, h = q / KB;
         const WT* Gs = sp ? G1 : G0;
@@ -473,7 +477,7 @@ struct Fast {
           }
         }
         if (lane == 0) {
-          L.cnt[0] = m;
+          L.cnt[par] = m;
           ldrun[0] += log(ldu);
           ldrun[1] += log(ldd);
           if (flg) atomicOr(&c.st->flags, flg);
@@ -482,7 +486,7 @@ struct Fast {
       }
       __syncthreads();
       clk.stop(c.st, PH_DECIDE);
-      const int m = L.cnt[0];
+      const int m = L.cnt[par];
       acc_total += m;
       if (m == 0) continue;
       const int mp = (m + 3) & ~3;

@@ -94,6 +94,24 @@ def test_emulated_sweeps_match_oracle(plain, tmp_path, name, n, sweeps, variant)
 # and 16), FP64 and FP32 wraps; square 5x5 (N = 25) and 6x6 (N = 36) pad with idle sites
 _SMALL = {L: di.Workload(f"square{L}x{L}_U4_b1", 9, "square", L, 4.0, 1.0, 0.1, 2, 1, 5)
           for L in (4, 5, 6)}
+# U = 16: acceptance about 0.28, so whole blocks of 8 sites go without an accept (the path on
+# which the next block's count is written while other waves may still read this one's)
+_LOW_ACCEPT = di.Workload("square6x6_U16_b2", 9, "square", 6, 16.0, 2.0, 0.1, 4, 1, 10)
+
+
+def test_emulated_blocks_without_accepts_match_oracle(plain, tmp_path):
+    from oracle import Model, OracleChains
+    w = _LOW_ACCEPT
+    n, sweeps = 4, 2
+    _write_case(tmp_path, w, n, sweeps, "fp64", 0, 1.0, delay_rank=8)
+    _run(plain["run_chains"], tmp_path)
+    obs, green, fields = _outputs(tmp_path, w, n)
+    assert float(obs["accepted"].sum()) / float(obs["attempted"].sum()) < 0.35
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), w.fields(n), w.seeds(n))
+    oc.sweep(sweeps)
+    for c in range(n):
+        assert np.array_equal(fields[c], oc.fields()[c]), c
+        assert np.max(np.abs(green[c] - oc.green()[c])) / max(1.0, np.max(np.abs(oc.green()[c]))) < 1e-10
 
 
 @pytest.mark.parametrize("L,k,np_", [(4, 8, 16), (5, 8, 32), (5, 16, 32), (6, 8, 64), (6, 16, 64)])
@@ -250,6 +268,10 @@ def test_emulated_kernels_under_sanitizers(tmp_path, sanitizer):
         _write_case(d, di.WORKLOADS[name], 1, sweeps, precision, refresh, 1.0)
         log = _run(exes["run_chains"], d, timeout=3600, env=env)
         assert "Sanitizer" not in log, (name, precision, log[-3000:])
+    d = tmp_path / "low_accept"
+    _write_case(d, _LOW_ACCEPT, 2, 2, "fp64", 0, 1.0, delay_rank=8)
+    log = _run(exes["run_chains"], d, timeout=3600, env=env)
+    assert "Sanitizer" not in log, log[-3000:]
     for L, k in ((5, 8), (5, 16), (6, 8), (6, 16)):
         for precision in ("fp64", "fp32"):
             d = tmp_path / f"small{L}_{k}_{precision}"
