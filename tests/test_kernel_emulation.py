@@ -99,6 +99,32 @@ _SMALL = {L: di.Workload(f"square{L}x{L}_U4_b1", 9, "square", L, 4.0, 1.0, 0.1, 
 _LOW_ACCEPT = di.Workload("square6x6_U16_b2", 9, "square", 6, 16.0, 2.0, 0.1, 4, 1, 10)
 
 
+# degenerate and ragged shapes: one site, stabilisation every slice, slice counts that are not a
+# multiple of the interval, odd and honeycomb lattices, blocks of 16 over 49 sites
+_EDGE = [  # name, lattice, L, U, beta, stab, delay rank, sweeps
+    ("one_site", "square", 1, 4.0, 1.0, 3, 0, 2),
+    ("stab_every_slice", "square", 2, 4.0, 0.5, 1, 0, 2),
+    ("slices_23_stab_10", "square", 4, 4.0, 2.3, 10, 0, 2),
+    ("odd_3x3_U6", "square", 3, 6.0, 0.7, 2, 0, 3),
+    ("honeycomb_2x2", "honeycomb", 2, 3.0, 1.0, 4, 0, 2),
+    ("square7x7_k16", "square", 7, 4.0, 0.6, 10, 16, 1),
+]
+
+
+@pytest.mark.parametrize("name,lattice,L,U,beta,stab,k,sweeps", _EDGE)
+def test_emulated_edge_shapes_match_oracle(plain, tmp_path, name, lattice, L, U, beta, stab, k, sweeps):
+    from oracle import Model, OracleChains
+    w = di.Workload(name, 9, lattice, L, U, beta, 0.1, 2, sweeps, stab)
+    _write_case(tmp_path, w, 2, sweeps, "fp64", 0, 1.0, delay_rank=k)
+    _run(plain["run_chains"], tmp_path)
+    obs, green, fields = _outputs(tmp_path, w, 2)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every), w.fields(2), w.seeds(2))
+    oc.sweep(sweeps)
+    assert np.array_equal(fields, oc.fields())
+    assert np.max(np.abs(green - oc.green())) < 1e-10
+    assert not np.any(obs["flags"])
+
+
 def test_emulated_blocks_without_accepts_match_oracle(plain, tmp_path):
     from oracle import Model, OracleChains
     w = _LOW_ACCEPT
