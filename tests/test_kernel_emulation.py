@@ -9,9 +9,10 @@ the workspace kernels execute work-item by work-item with the wavefront collecti
   give bit for bit the result of the same request alone;
 * sweep modes and the per-sweep series against the oracle, the allocation-free entry point
   against the workspace path, the Ising sweep against its oracle bit for bit;
-* with DQMC_EMU_SANITIZERS=1 the same runs under AddressSanitizer (no access outside any
-  buffer: workspace, LDS, stacks) and ThreadSanitizer (no two work-items touch the same LDS or
-  workspace location without a barrier ordering them).
+* with DQMC_EMU_SANITIZERS=1 the same kinds of runs (every N <= 64 instantiation, low acceptance,
+  sweep modes, series, the static entry point, serving, Ising) under AddressSanitizer (no access
+  outside any buffer: workspace, LDS, stacks) and ThreadSanitizer (no two work-items touch the
+  same LDS or workspace location without a barrier ordering them).
 
 The GPU is not involved; the package never loads the emulation.
 """
@@ -298,6 +299,21 @@ def test_emulated_kernels_under_sanitizers(tmp_path, sanitizer):
     _write_case(d, _LOW_ACCEPT, 2, 2, "fp64", 0, 1.0, delay_rank=8)
     log = _run(exes["run_chains"], d, timeout=3600, env=env)
     assert "Sanitizer" not in log, log[-3000:]
+    w4 = di.WORKLOADS["square4x4_U4_b2"]
+    for tag, kw in (("modes_fp32", dict(precision="fp32", refresh=3, sweep_mode=3)),
+                    ("series_alternating", dict(precision="fp64", refresh=0, sweep_mode=1, series=1)),
+                    ("static_fp32", dict(precision="fp32", refresh=3, static=1))):
+        d = tmp_path / tag
+        _write_case(d, w4, 2, 2, kw.pop("precision"), kw.pop("refresh"), 1.0, **kw)
+        log = _run(exes["run_chains"], d, timeout=3600, env=env)
+        assert "Sanitizer" not in log, (tag, log[-3000:])
+    for L, n, sw in ((2, 3, 20), (16, 2, 5), (64, 1, 2)):
+        d = tmp_path / f"ising{L}"
+        d.mkdir()
+        np.asarray(di.chain_seeds(7, n, L), dtype=np.uint64).tofile(d / "seeds.bin")
+        r = subprocess.run([exes["ising_chains"], str(d), str(L), "2.269", str(n), str(sw)], capture_output=True,
+                           text=True, timeout=3600, env=dict(os.environ, **env))
+        assert r.returncode == 0 and "Sanitizer" not in r.stderr, (L, r.stderr[-3000:])
     for L, k in ((5, 8), (5, 16), (6, 8), (6, 16)):
         for precision in ("fp64", "fp32"):
             d = tmp_path / f"small{L}_{k}_{precision}"
