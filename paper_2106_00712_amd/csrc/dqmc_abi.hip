@@ -483,8 +483,10 @@ dqmc_status make_layout(const dqmc_model* m, int32_t n_chains, Layout* out, bool
     L.o_xy = L.KT ? ctake((4 * (size_t)L.np * L.KT + 4 * (size_t)L.np * K16 + 4 * (size_t)L.KT * K16) * wts)
                   : ctake(4 * (size_t)L.np * L.K * wts);
     // blocked factorisations (np <= QR_BLOCK_MAX_NP): QR reflectors (np x np) and one QB x QB
-    // T per panel; the Gauss-Jordan solve reuses the first 3 QB np doubles
-    L.o_qrv = (L.np <= QR_BLOCK_MAX_NP) ? ctake((nn + (size_t)QB * L.np) * 8) : 0;
+    // T per panel; the Gauss-Jordan solve reuses the area for its np x QB and QB x 2np panels
+    // (3 QB np doubles, more than the QR's np^2 + QB np below np = 2 QB)
+    L.o_qrv = (L.np <= QR_BLOCK_MAX_NP)
+                  ? ctake(std::max(nn + (size_t)QB * L.np, 3 * (size_t)QB * L.np) * 8) : 0;
     // left UDT stack of the alternating sweeps, laid out like the right stack
     L.o_lstack = (m->sweep_mode & 1) ? ctake(2 * (size_t)L.J * (2 * nn + L.np) * 8) : 0;
   } else {

@@ -126,6 +126,27 @@ def test_emulated_edge_shapes_match_oracle(plain, tmp_path, name, lattice, L, U,
     assert not np.any(obs["flags"])
 
 
+def test_emulated_workspace_kernel_at_padded_size_16_with_several_chains(plain, tmp_path):
+    """Sweep modes run in the workspace kernels at any N; at padded size 16 the blocked
+    Gauss-Jordan's panels (3 x 16 x 16 doubles) are larger than the QR area they reuse, and an
+    area sized for the QR alone let them run into the next chain's state (caught here as garbage
+    in chains 1 and 2, and by AddressSanitizer past the workspace's end)."""
+    from oracle import Model, OracleChains
+    w = di.Workload("square4x4_U8_b1.7", 9, "square", 4, 8.0, 1.7, 0.1, 3, 1, 1)
+    _write_case(tmp_path, w, 3, 1, "fp64", 0, 1.0, sweep_mode=2)
+    log = _run(plain["run_chains"], tmp_path)
+    assert "variant 1" in log, log
+    obs, green, fields = _outputs(tmp_path, w, 3)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, sweep_mode=2), w.fields(3),
+                      w.seeds(3))
+    oc.sweep(1)
+    om = oc.measure()
+    assert np.array_equal(fields, oc.fields())
+    assert [int(x) for x in obs["accepted"]] == [m["accepted"] for m in om]
+    assert not np.any(obs["flags"])
+    assert np.max(np.abs(green - oc.green())) < 1e-10
+
+
 def test_emulated_blocks_without_accepts_match_oracle(plain, tmp_path):
     from oracle import Model, OracleChains
     w = _LOW_ACCEPT
