@@ -147,6 +147,45 @@ def test_emulated_workspace_kernel_at_padded_size_16_with_several_chains(plain, 
     assert np.max(np.abs(green - oc.green())) < 1e-10
 
 
+def _random_shapes(n_cases, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_cases):
+        lattice = str(rng.choice(["square", "honeycomb"]))
+        L = int(rng.integers(1, 7)) if lattice == "square" else int(rng.integers(2, 5))
+        out.append(dict(name=f"random{i}", lattice=lattice, L=L, U=float(rng.choice([0.0, 2.0, 4.0, 8.0])),
+                        beta=float(rng.choice([0.1, 0.3, 0.5, 1.0, 1.7])), stab=int(rng.integers(1, 12)),
+                        k=int(rng.choice([0, 4, 8, 12, 16, 32])), mode=int(rng.choice([0, 0, 0, 1, 2, 3])),
+                        chains=int(rng.integers(1, 4)), sweeps=int(rng.integers(1, 4))))
+    return out
+
+
+@pytest.mark.parametrize("shape", _random_shapes(10, 2024), ids=lambda s: s["name"])
+def test_emulated_random_shapes_match_oracle(plain, tmp_path, shape):
+    """Seeded random models (lattice, size, U, beta, stabilisation interval, delay rank, sweep
+    mode, chains, sweeps): fields bit for bit and G(0) to 1e-10 against the oracle, or a near tie
+    counted on either side."""
+    from oracle import Model, OracleChains
+    sh = shape
+    w = di.Workload(sh["name"], 9, sh["lattice"], sh["L"], sh["U"], sh["beta"], 0.1, sh["chains"], sh["sweeps"],
+                    sh["stab"])
+    n = sh["chains"]
+    _write_case(tmp_path, w, n, sh["sweeps"], "fp64", 0, 1.0, sweep_mode=sh["mode"], delay_rank=sh["k"])
+    _run(plain["run_chains"], tmp_path)
+    obs, green, fields = _outputs(tmp_path, w, n)
+    oc = OracleChains(Model(w.hopping(), w.U, w.dtau, w.n_slices, w.stab_every, sweep_mode=sh["mode"]),
+                      w.fields(n), w.seeds(n))
+    oc.sweep(sh["sweeps"])
+    om = oc.measure()
+    for c in range(n):
+        if obs["near_ties"][c] or om[c]["near_ties"]:
+            continue
+        assert np.array_equal(fields[c], oc.fields()[c]), (sh, c)
+        ref = oc.green()[c]
+        assert np.max(np.abs(green[c] - ref)) / max(1.0, np.max(np.abs(ref))) < 1e-10, (sh, c)
+    assert not np.any(obs["flags"])
+
+
 def test_emulated_blocks_without_accepts_match_oracle(plain, tmp_path):
     from oracle import Model, OracleChains
     w = _LOW_ACCEPT
