@@ -3,7 +3,8 @@
 // one-sweep dqmc_sweep calls, dqmc_measure and dqmc_get_fields, and writes obs.bin, green.bin and
 // fields_out.bin to DIR.  The workspace is one exact-size heap block, so AddressSanitizer sees
 // any access past it; EMU_WS_FILL and EMU_LDS_FILL set the bytes the workspace and LDS start with.
-// An optional second line of header.txt, "sweep_mode series static", selects the sweep mode
+// An optional second line of header.txt, "sweep_mode series static [qr_blocked=1]", selects the
+// blocked stabilisation QR (dqmc_model.qr_blocked) and the sweep mode
 // (dqmc_model.sweep_mode), dqmc_sweep_series in place of the one-sweep calls (series.bin,
 // [n_sweeps][n_chains][4]), or the allocation-free dqmc_run_static in place of the whole
 // sequence.  An optional third line "slice n_wraps" adds the fixed-field probe
@@ -40,8 +41,9 @@ int main(int argc, char** argv) {
   double drift, U, dtau;
   if (std::fscanf(h, "%d %d %d %d %d %d %lf %lf %lf %d %d %d", &n, &L, &stab, &prec, &refresh, &k, &drift, &U,
                   &dtau, &n_chains, &n_sweeps, &have_fields) != 12) return 2;
-  int sweep_mode = 0, use_series = 0, use_static = 0;
+  int sweep_mode = 0, use_series = 0, use_static = 0, qr_blocked = 0;
   if (std::fscanf(h, "%d %d %d", &sweep_mode, &use_series, &use_static) != 3) sweep_mode = use_series = use_static = 0;
+  if (std::fscanf(h, " qr_blocked=%d", &qr_blocked) != 1) qr_blocked = 0;
   int probe_slice = -1, probe_wraps = 0;
   if (std::fscanf(h, "%d %d", &probe_slice, &probe_wraps) != 2) probe_slice = -1;
   std::fclose(h);
@@ -54,6 +56,7 @@ int main(int argc, char** argv) {
   m.stab_every = stab; m.refresh_every = refresh; m.delay_rank = k;
   m.precision = prec ? DQMC_FP32_WRAP : DQMC_FP64; m.drift_limit = drift;
   m.sweep_mode = sweep_mode;
+  m.qr_blocked = qr_blocked;
   if (use_static) {
     std::vector<dqmc_obs> obs(n_chains);
     std::vector<double> green((size_t)n_chains * 2 * n * n);
