@@ -3,7 +3,9 @@ the N <= 64 register/LDS sweep kernel, the initialisation, constants and measure
 the workspace kernels execute work-item by work-item with the wavefront collectives emulated.
 
 * parity: fields after the sweeps equal the oracle's bit for bit and G(0) agrees to 1e-10
-  (square 4x4 over two sweeps, square 8x8 and honeycomb 6x6 over one), as on the GPU;
+  (square 4x4 over two sweeps, square 8x8 and honeycomb 6x6 over one, every instantiation of the
+  N <= 64 kernel, degenerate and ragged shapes, seeded random models, blocks without accepts at
+  U = 16, the workspace kernels at padded size 16 with several chains), as on the GPU;
 * FP32 wraps: chains stay at half filling with drift of the FP32 order;
 * continuous batching: requests served through slot re-initialisation and per-chain sweep counts
   give bit for bit the result of the same request alone;
