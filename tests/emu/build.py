@@ -1,6 +1,6 @@
 """Builds the test-only host emulation of the library (emu_hip.h): the library's sources, with the
 few device-only constructs rewritten, compiled for the host with clang++ together with the fiber
-runtime and three drivers (run_chains, serve_chains, ising_chains).
+runtime and four drivers (run_chains, serve_chains, ising_chains, multi_chains).
 
 Rewrites (applied to copies under tests/emu/_build/<variant>/src, never to the sources):
   * the dynamic LDS declaration becomes the emulated workgroup's LDS buffer;
@@ -28,7 +28,7 @@ FLAGS = {
     "tsan": ["-O1", "-g", "-fsanitize=thread", "-DEMU_TSAN"],
 }
 
-DRIVERS = ("run_chains", "serve_chains", "ising_chains")
+DRIVERS = ("run_chains", "serve_chains", "ising_chains", "multi_chains")
 
 REWRITES = [
     (re.compile(r"extern __shared__ double lds\[\];"), "double* lds = emu::dyn_lds();"),

@@ -8,7 +8,8 @@ the workspace kernels execute work-item by work-item with the wavefront collecti
   U = 16, the workspace kernels at padded size 16 with several chains), as on the GPU;
 * FP32 wraps: chains stay at half filling with drift of the FP32 order;
 * continuous batching: requests served through slot re-initialisation and per-chain sweep counts
-  give bit for bit the result of the same request alone;
+  give bit for bit the result of the same request alone; batches of two lattices swept together
+  (dqmc_sweep_multi, graph replays) equal the batches swept one at a time;
 * sweep modes and the per-sweep series against the oracle, the allocation-free entry point
   against the workspace path, the Ising sweep against its oracle bit for bit;
 * with DQMC_EMU_SANITIZERS=1 the same kinds of runs (every N <= 64 instantiation, low acceptance,
@@ -343,6 +344,16 @@ def test_emulated_serving_same_alone_and_in_the_mix(plain, args, n_req):
     r = subprocess.run([plain["serve_chains"], *args], capture_output=True, text=True, timeout=1800)
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
     assert r.stdout.count(": same") == n_req
+
+
+def test_emulated_multi_batch_and_graph_replays(plain):
+    """A 4x4 batch (register/LDS kernel) and a 10x10 batch (workspace kernel) swept together by
+    dqmc_sweep_multi and by three replays of a recorded graph equal the same batches swept one at
+    a time (the GPU case of this pair is off, see the batching GPU tests)."""
+    r = subprocess.run([plain["multi_chains"], "4", "10", "0.3", "1", "2", "1"], capture_output=True,
+                       text=True, timeout=1800)
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
+    assert r.stdout.count(": same") == 4
 
 
 @pytest.mark.skipif(not SANITIZERS, reason="set DQMC_EMU_SANITIZERS=1 (builds two sanitizer variants, minutes)")
